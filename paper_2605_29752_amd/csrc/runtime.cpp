@@ -1,0 +1,569 @@
+// smoothgemm host runtime: contexts, the per-call GEMM entry points, plan execution, the sweep
+// driver and the landscape metrics.  The dispatch-table construction lives in table.cpp.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+
+#include "sg_internal.h"
+#include "sg_table.h"
+
+namespace sg {
+
+static thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+    g_err = std::string(what) + ": " + hipGetErrorString(e);
+    return SG_EHIP;
+}
+
+}  // namespace sg
+
+using namespace sg;
+
+struct sg_ctx {
+    int device = 0;
+    int num_cus = 0;
+    int plain_variant = 0;
+    void* ws = nullptr;
+    size_t ws_bytes = 0;
+    const sg_table* table = nullptr;
+    std::vector<hipEvent_t> events;
+    // accounting of the most recent sweep (timed runs only)
+    std::vector<int64_t> acct_launches;
+    std::vector<double> acct_seconds;
+    std::vector<double> acct_flops;
+};
+
+namespace {
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+int ensure_ws(sg_ctx* ctx, size_t bytes) {
+    if (bytes <= ctx->ws_bytes) return SG_OK;
+    size_t want = std::max(bytes, ctx->ws_bytes * 2);
+    want = (want + 0xFFFFF) & ~size_t(0xFFFFF);
+    void* p = nullptr;
+    if (ctx->ws) {
+        // the old buffer may still be read by queued work: wait for the device first
+        SG_HIP(hipDeviceSynchronize());
+        SG_HIP(hipFree(ctx->ws));
+        ctx->ws = nullptr;
+        ctx->ws_bytes = 0;
+    }
+    if (hipMalloc(&p, want) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(SG_ENOMEM, "workspace allocation of " + std::to_string(want) + " bytes failed");
+    }
+    ctx->ws = p;
+    ctx->ws_bytes = want;
+    return SG_OK;
+}
+
+// One leaf of an execution plan: a sub-problem run by one variant.
+struct Leaf {
+    int64_t m0, n0, k0, m, n, k;  // data region (elements)
+    int64_t Ml, Nl, Kl;           // launch extent (>= data; padding)
+    int variant;
+    bool first, last;             // first / last piece along K of its output region
+};
+
+// Expand the table plan of a problem of actual size (m, n, k) at offset (m0, n0, k0).
+// `cell` is the grid cell whose record applies (sizes in steps).  A split point at or beyond
+// the actual extent drops the empty piece and runs the covering piece's plan on the whole
+// region (its cell still covers it).
+void expand_plan(const sg_table* t, int64_t m0, int64_t n0, int64_t k0, int64_t m, int64_t n,
+                 int64_t k, int cm, int cn, int ck, bool first, bool last, std::vector<Leaf>& out) {
+    const int g = t->grid.step;
+    const int64_t c = t->cell_index(cm, cn, ck);
+    const int act = t->action[c];
+    const int arg = t->arg[c];
+    if (act == SG_ACT_AS_IS || act == SG_ACT_PAD) {
+        Leaf L;
+        L.m0 = m0; L.n0 = n0; L.k0 = k0; L.m = m; L.n = n; L.k = k;
+        int64_t run = (act == SG_ACT_AS_IS) ? c : arg;
+        int rm, rn, rk;
+        t->cell_coords(run, &rm, &rn, &rk);
+        if (act == SG_ACT_PAD) {
+            L.Ml = std::max<int64_t>(m, (int64_t)(rm + 1) * g);
+            L.Nl = std::max<int64_t>(n, (int64_t)(rn + 1) * g);
+            L.Kl = std::max<int64_t>(k, (int64_t)(rk + 1) * g);
+        } else {
+            L.Ml = m; L.Nl = n; L.Kl = k;
+        }
+        L.variant = t->best_var[run];
+        L.first = first;
+        L.last = last;
+        out.push_back(L);
+        return;
+    }
+    const int64_t p = (int64_t)arg * g;  // split point in elements
+    if (act == SG_ACT_SPLIT_M) {
+        if (p >= m) { expand_plan(t, m0, n0, k0, m, n, k, arg - 1, cn, ck, first, last, out); return; }
+        expand_plan(t, m0, n0, k0, p, n, k, arg - 1, cn, ck, first, last, out);
+        expand_plan(t, m0 + p, n0, k0, m - p, n, k, cm - arg, cn, ck, first, last, out);
+    } else if (act == SG_ACT_SPLIT_N) {
+        if (p >= n) { expand_plan(t, m0, n0, k0, m, n, k, cm, arg - 1, ck, first, last, out); return; }
+        expand_plan(t, m0, n0, k0, m, p, k, cm, arg - 1, ck, first, last, out);
+        expand_plan(t, m0, n0 + p, k0, m, n - p, k, cm, cn - arg, ck, first, last, out);
+    } else {
+        if (p >= k) { expand_plan(t, m0, n0, k0, m, n, k, cm, cn, arg - 1, first, last, out); return; }
+        expand_plan(t, m0, n0, k0, m, n, p, cm, cn, arg - 1, first, false, out);
+        expand_plan(t, m0, n0, k0 + p, m, n, k - p, cm, cn, ck - arg, false, last, out);
+    }
+}
+
+struct Problem {
+    int64_t M, N, K;
+    const uint16_t* A; int64_t lda;
+    const uint16_t* B; int64_t ldb;
+    void* C; int64_t ldc;
+    int c_bf16;
+    int beta;
+};
+
+// Plan of one call as a list of leaves (single leaf for PLAIN / VARIANT / BEST).
+int make_plan(const sg_ctx* ctx, const Problem& pr, int mode, int variant, std::vector<Leaf>& leaves) {
+    leaves.clear();
+    if (mode == SG_MODE_DEFAULT) mode = ctx->table ? SG_MODE_DP : SG_MODE_PLAIN;
+    if (mode == SG_MODE_PLAIN || mode == SG_MODE_VARIANT) {
+        const int v = (mode == SG_MODE_PLAIN) ? ctx->plain_variant : variant;
+        if (v < 0 || v >= kNumVariants) return fail(SG_EINVAL, "variant out of range");
+        leaves.push_back(Leaf{0, 0, 0, pr.M, pr.N, pr.K, pr.M, pr.N, pr.K, v, true, true});
+        return SG_OK;
+    }
+    if (mode != SG_MODE_BEST && mode != SG_MODE_DP) return fail(SG_EINVAL, "unknown mode");
+    const sg_table* t = ctx->table;
+    if (!t) return fail(SG_ENOTABLE, "table-driven mode requested but no dispatch table is set");
+    int cm, cn, ck;
+    if (!t->covering_cell(pr.M, pr.N, pr.K, &cm, &cn, &ck))
+        return fail(SG_ERANGE, "shape outside the dispatch table's grid");
+    if (mode == SG_MODE_BEST) {
+        const int v = t->best_var[t->cell_index(cm, cn, ck)];
+        leaves.push_back(Leaf{0, 0, 0, pr.M, pr.N, pr.K, pr.M, pr.N, pr.K, v, true, true});
+        return SG_OK;
+    }
+    expand_plan(t, 0, 0, 0, pr.M, pr.N, pr.K, cm, cn, ck, true, true, leaves);
+    return SG_OK;
+}
+
+// Workspace layout: [plan accumulator M*N FP32 (only for BF16 output with a K split)]
+//                   [split-K partials of the largest leaf].
+size_t plan_workspace(const Problem& pr, const std::vector<Leaf>& leaves, size_t* acc_bytes) {
+    bool ksplit = false;
+    size_t part = 0;
+    for (const Leaf& L : leaves) {
+        if (!(L.first && L.last)) ksplit = true;
+        LaunchDesc d{};
+        d.M = L.m; d.N = L.n; d.K = L.k; d.Ml = L.Ml; d.Nl = L.Nl; d.Kl = L.Kl;
+        part = std::max(part, launch_workspace_bytes(L.variant, d));
+    }
+    size_t acc = (ksplit && pr.c_bf16) ? (size_t)pr.M * (size_t)pr.N * sizeof(float) : 0;
+    acc = (acc + 255) & ~size_t(255);
+    *acc_bytes = acc;
+    return acc + part;
+}
+
+// Enqueue one leaf.  Output routing (C FP32: accumulate in place; C BF16 with a K split:
+// accumulate in the FP32 plan accumulator W and round once in the last piece).
+int run_leaf(const Problem& pr, const Leaf& L, void* ws, size_t acc_bytes, hipStream_t s) {
+    LaunchDesc d{};
+    d.M = L.m; d.N = L.n; d.K = L.k; d.Ml = L.Ml; d.Nl = L.Nl; d.Kl = L.Kl;
+    d.A = pr.A + L.m0 * pr.lda + L.k0; d.lda = pr.lda;
+    d.B = pr.B + L.k0 * pr.ldb + L.n0; d.ldb = pr.ldb;
+    const int64_t coff = L.m0 * pr.ldc + L.n0;
+    float* W = (float*)ws;
+    const int64_t woff = L.m0 * pr.N + L.n0;
+    if (!pr.c_bf16) {
+        d.C = (float*)pr.C + coff; d.ldc = pr.ldc; d.out_bf16 = 0;
+        const bool accumulate = !L.first || pr.beta;
+        d.add = accumulate ? d.C : nullptr; d.ldadd = pr.ldc; d.add_kind = accumulate ? ADD_F32 : ADD_NONE;
+    } else if (L.first && L.last) {
+        d.C = (uint16_t*)pr.C + coff; d.ldc = pr.ldc; d.out_bf16 = 1;
+        d.add = pr.beta ? d.C : nullptr; d.ldadd = pr.ldc; d.add_kind = pr.beta ? ADD_BF16 : ADD_NONE;
+    } else if (!L.last) {
+        d.C = W + woff; d.ldc = pr.N; d.out_bf16 = 0;
+        if (L.first) {
+            d.add = pr.beta ? (const void*)((uint16_t*)pr.C + coff) : nullptr;
+            d.ldadd = pr.ldc; d.add_kind = pr.beta ? ADD_BF16 : ADD_NONE;
+        } else {
+            d.add = W + woff; d.ldadd = pr.N; d.add_kind = ADD_F32;
+        }
+    } else {  // last piece of a K split, BF16 output: round (W + acc) once
+        d.C = (uint16_t*)pr.C + coff; d.ldc = pr.ldc; d.out_bf16 = 1;
+        d.add = W + woff; d.ldadd = pr.N; d.add_kind = ADD_F32;
+    }
+    return launch_variant(L.variant, d, (char*)ws + acc_bytes, s);
+}
+
+__global__ void sg_scale_zero_f32(float* C, int64_t ldc, int64_t M, int64_t N) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < M * N;
+         i += (int64_t)gridDim.x * blockDim.x)
+        C[(i / N) * ldc + i % N] = 0.0f;
+}
+__global__ void sg_scale_zero_bf16(uint16_t* C, int64_t ldc, int64_t M, int64_t N) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < M * N;
+         i += (int64_t)gridDim.x * blockDim.x)
+        C[(i / N) * ldc + i % N] = 0;
+}
+
+int validate(const sg_gemm_args* a) {
+    if (!a) return fail(SG_EINVAL, "NULL args");
+    if (a->M < 0 || a->N < 0 || a->K < 0) return fail(SG_EINVAL, "negative dimension");
+    if (a->c_dtype != SG_F32 && a->c_dtype != SG_BF16) return fail(SG_EINVAL, "bad c_dtype");
+    if (a->beta != 0 && a->beta != 1) return fail(SG_EINVAL, "beta must be 0 or 1");
+    if (a->mode < SG_MODE_DEFAULT || a->mode > SG_MODE_VARIANT) return fail(SG_EINVAL, "bad mode");
+    if (a->M == 0 || a->N == 0) return SG_OK;
+    if (!a->C) return fail(SG_EINVAL, "NULL C with non-zero size");
+    if (a->ldc < a->N) return fail(SG_EINVAL, "ldc < N");
+    if (a->K > 0) {
+        if (!a->A || !a->B) return fail(SG_EINVAL, "NULL A or B with non-zero size");
+        if (a->lda < a->K || a->ldb < a->N) return fail(SG_EINVAL, "leading dimension too small");
+    }
+    if (a->M > 0x7FFFFFFF || a->N > 0x7FFFFFFF || a->K > 0x7FFFFFFF)
+        return fail(SG_EINVAL, "dimension exceeds 2^31 - 1");
+    return SG_OK;
+}
+
+int gemm_impl(sg_ctx* ctx, const sg_gemm_args* a, hipStream_t s, std::vector<Leaf>* keep = nullptr) {
+    int rc = validate(a);
+    if (rc) return rc;
+    if (a->M == 0 || a->N == 0) return SG_OK;
+    if (a->K == 0) {
+        if (a->beta) return SG_OK;
+        int64_t blocks = std::min<int64_t>((a->M * a->N + 255) / 256, 65536);
+        if (a->c_dtype == SG_F32)
+            hipLaunchKernelGGL(sg_scale_zero_f32, dim3((unsigned)blocks), dim3(256), 0, s,
+                               (float*)a->C, a->ldc, a->M, a->N);
+        else
+            hipLaunchKernelGGL(sg_scale_zero_bf16, dim3((unsigned)blocks), dim3(256), 0, s,
+                               (uint16_t*)a->C, a->ldc, a->M, a->N);
+        SG_HIP(hipGetLastError());
+        return SG_OK;
+    }
+    Problem pr{a->M, a->N, a->K, (const uint16_t*)a->A, a->lda, (const uint16_t*)a->B, a->ldb,
+               a->C, a->ldc, a->c_dtype == SG_BF16, a->beta};
+    std::vector<Leaf> local;
+    std::vector<Leaf>& leaves = keep ? *keep : local;
+    rc = make_plan(ctx, pr, a->mode, a->variant, leaves);
+    if (rc) return rc;
+    size_t acc_bytes = 0;
+    size_t need = plan_workspace(pr, leaves, &acc_bytes);
+    rc = ensure_ws(ctx, need);
+    if (rc) return rc;
+    for (const Leaf& L : leaves) {
+        rc = run_leaf(pr, L, ctx->ws, acc_bytes, s);
+        if (rc) return rc;
+    }
+    return SG_OK;
+}
+
+std::mutex g_default_mu;
+sg_ctx* g_default[64] = {nullptr};
+
+}  // namespace
+
+extern "C" {
+
+const char* sg_last_error(void) { return g_err.c_str(); }
+const char* sg_version(void) { return "smoothgemm 0.1 (gfx950)"; }
+
+int sg_ctx_create(int device, sg_ctx** out) {
+    if (!out) return fail(SG_EINVAL, "NULL out");
+    *out = nullptr;
+    int n = 0;
+    SG_HIP(hipGetDeviceCount(&n));
+    if (device < 0 || device >= n) return fail(SG_EINVAL, "no such device");
+    DeviceGuard guard(device);
+    hipDeviceProp_t prop;
+    SG_HIP(hipGetDeviceProperties(&prop, device));
+    sg_ctx* c = new (std::nothrow) sg_ctx();
+    if (!c) return fail(SG_ENOMEM, "context allocation failed");
+    c->device = device;
+    c->num_cus = prop.multiProcessorCount;
+    c->acct_launches.assign(kNumVariants, 0);
+    c->acct_seconds.assign(kNumVariants, 0.0);
+    c->acct_flops.assign(kNumVariants, 0.0);
+    *out = c;
+    return SG_OK;
+}
+
+int sg_ctx_destroy(sg_ctx* ctx) {
+    if (!ctx) return SG_OK;
+    DeviceGuard guard(ctx->device);
+    for (hipEvent_t e : ctx->events) (void)hipEventDestroy(e);
+    if (ctx->ws) {
+        (void)hipDeviceSynchronize();
+        (void)hipFree(ctx->ws);
+    }
+    delete ctx;
+    return SG_OK;
+}
+
+int sg_ctx_set_plain_variant(sg_ctx* ctx, int variant) {
+    if (!ctx) return fail(SG_EINVAL, "NULL ctx");
+    if (variant < 0 || variant >= kNumVariants) return fail(SG_EINVAL, "variant out of range");
+    ctx->plain_variant = variant;
+    return SG_OK;
+}
+
+int sg_ctx_reserve_workspace(sg_ctx* ctx, size_t bytes) {
+    if (!ctx) return fail(SG_EINVAL, "NULL ctx");
+    DeviceGuard guard(ctx->device);
+    return ensure_ws(ctx, bytes);
+}
+
+int sg_ctx_set_table(sg_ctx* ctx, const sg_table* t) {
+    if (!ctx) return fail(SG_EINVAL, "NULL ctx");
+    ctx->table = t;
+    return SG_OK;
+}
+
+int gemm_bf16_nn(int64_t M, int64_t N, int64_t K, const void* A, const void* B, void* C) {
+    int dev = 0;
+    SG_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) return fail(SG_EINVAL, "device ordinal too large");
+    sg_ctx* ctx;
+    {
+        std::lock_guard<std::mutex> lk(g_default_mu);
+        if (!g_default[dev]) {
+            int rc = sg_ctx_create(dev, &g_default[dev]);
+            if (rc) return rc;
+        }
+        ctx = g_default[dev];
+    }
+    sg_gemm_args a{};
+    a.M = M; a.N = N; a.K = K;
+    a.A = A; a.lda = K; a.B = B; a.ldb = N; a.C = C; a.ldc = N;
+    a.c_dtype = SG_F32; a.beta = 0; a.mode = SG_MODE_DEFAULT; a.variant = 0;
+    std::lock_guard<std::mutex> lk(g_default_mu);
+    return gemm_impl(ctx, &a, nullptr);
+}
+
+int gemm_bf16_nn_ex(sg_ctx* ctx, const sg_gemm_args* args, void* stream) {
+    if (!ctx) return fail(SG_EINVAL, "NULL ctx");
+    DeviceGuard guard(ctx->device);
+    return gemm_impl(ctx, args, (hipStream_t)stream);
+}
+
+int sg_num_variants(void) { return kNumVariants; }
+
+int sg_variant_info_get(int v, sg_variant_info* out) {
+    if (!out || v < 0 || v >= kNumVariants) return fail(SG_EINVAL, "bad variant or NULL out");
+    const TileShape& t = kTiles[variant_tile(v)];
+    out->id = v;
+    out->bm = t.bm;
+    out->bn = t.bn;
+    out->bk = kBK;
+    out->splits = variant_splits(v);
+    out->threads = 256;
+    out->lds_bytes = lds_bytes_of_tile(variant_tile(v));
+    std::snprintf(out->name, sizeof out->name, "%dx%dx%d_s%d", t.bm, t.bn, kBK, out->splits);
+    return SG_OK;
+}
+
+double sg_roughness(const double* T, int64_t n) {
+    if (!T || n < 2) return NAN;
+    double s = 0.0;
+    for (int64_t i = 0; i + 1 < n; ++i) s += std::fabs(T[i + 1] - T[i]);
+    return s / (double)(n - 1);
+}
+
+int sg_landscape_stats(const double* tf, int nM, int nN, int nK, sg_stats* out) {
+    if (!tf || !out || nM < 2 || nN < 2 || nK < 2) return fail(SG_EINVAL, "stats need every axis >= 2");
+    auto at = [&](int m, int n, int k) { return tf[((int64_t)m * nN + n) * nK + k]; };
+    double sum = 0.0, peak = -INFINITY;
+    const int64_t total = (int64_t)nM * nN * nK;
+    for (int64_t i = 0; i < total; ++i) {
+        sum += tf[i];
+        peak = std::max(peak, tf[i]);
+    }
+    std::vector<double> line;
+    double rm = 0.0, rn = 0.0, rk = 0.0;
+    line.resize(nM);
+    for (int n = 0; n < nN; ++n)
+        for (int k = 0; k < nK; ++k) {
+            for (int m = 0; m < nM; ++m) line[m] = at(m, n, k);
+            rm += sg_roughness(line.data(), nM);
+        }
+    line.resize(nN);
+    for (int m = 0; m < nM; ++m)
+        for (int k = 0; k < nK; ++k) {
+            for (int n = 0; n < nN; ++n) line[n] = at(m, n, k);
+            rn += sg_roughness(line.data(), nN);
+        }
+    line.resize(nK);
+    for (int m = 0; m < nM; ++m)
+        for (int n = 0; n < nN; ++n) {
+            for (int k = 0; k < nK; ++k) line[k] = at(m, n, k);
+            rk += sg_roughness(line.data(), nK);
+        }
+    out->mean = sum / (double)total;
+    out->peak = peak;
+    out->rough_m = rm / ((double)nN * nK);
+    out->rough_n = rn / ((double)nM * nK);
+    out->rough_k = rk / ((double)nM * nN);
+    out->rough_3d = (out->rough_m + out->rough_n + out->rough_k) / 3.0;
+    return SG_OK;
+}
+
+int sg_fill_bf16(void* dst, int64_t n, uint64_t seed, uint64_t stream, int64_t offset, int kind,
+                 double scale, void* stream_handle) {
+    return launch_fill((uint16_t*)dst, n, seed, stream, offset, kind, scale, (hipStream_t)stream_handle);
+}
+
+}  // extern "C"
+
+// ---- sweep driver ----------------------------------------------------------------------------
+namespace sg {
+
+static int ensure_events(sg_ctx* ctx, size_t n) {
+    while (ctx->events.size() < n) {
+        hipEvent_t e;
+        SG_HIP(hipEventCreate(&e));
+        ctx->events.push_back(e);
+    }
+    return SG_OK;
+}
+
+// Time `reps` runs of the plan `leaves` (after one untimed run); every kernel launch is
+// bracketed by events.  Returns mean seconds per run; adds per-variant launch time to acct.
+int time_plan(sg_ctx* ctx, const Problem& pr, const std::vector<Leaf>& leaves, int reps,
+              hipStream_t s, double* sec, bool account) {
+    size_t acc_bytes = 0;
+    int rc = ensure_ws(ctx, plan_workspace(pr, leaves, &acc_bytes));
+    if (rc) return rc;
+    for (const Leaf& L : leaves) {
+        rc = run_leaf(pr, L, ctx->ws, acc_bytes, s);
+        if (rc) return rc;
+    }
+    const size_t nl = leaves.size();
+    const size_t ne = (size_t)reps * nl + 1;
+    rc = ensure_events(ctx, ne);
+    if (rc) return rc;
+    size_t e = 0;
+    for (int r = 0; r < reps; ++r)
+        for (const Leaf& L : leaves) {
+            SG_HIP(hipEventRecord(ctx->events[e++], s));
+            rc = run_leaf(pr, L, ctx->ws, acc_bytes, s);
+            if (rc) return rc;
+        }
+    SG_HIP(hipEventRecord(ctx->events[e], s));
+    SG_HIP(hipEventSynchronize(ctx->events[e]));
+    float total_ms = 0.f;
+    SG_HIP(hipEventElapsedTime(&total_ms, ctx->events[0], ctx->events[e]));
+    *sec = (double)total_ms * 1e-3 / reps;
+    if (account) {
+        e = 0;
+        for (int r = 0; r < reps; ++r)
+            for (const Leaf& L : leaves) {
+                float ms = 0.f;
+                SG_HIP(hipEventElapsedTime(&ms, ctx->events[e], ctx->events[e + 1]));
+                ++e;
+                ctx->acct_launches[L.variant] += 1;
+                ctx->acct_seconds[L.variant] += (double)ms * 1e-3;
+                ctx->acct_flops[L.variant] += 2.0 * (double)L.m * (double)L.n * (double)L.k;
+            }
+    }
+    return SG_OK;
+}
+
+}  // namespace sg
+
+extern "C" int sg_sweep(sg_ctx* ctx, const sg_shape* shapes, int64_t n, int mode, int variant,
+                        int c_dtype, int warmup, int reps, const void* A_pool, const void* B_pool,
+                        void* C_pool, double* out_sec, void* stream) {
+    if (!ctx || (n > 0 && (!shapes || !out_sec || !A_pool || !B_pool || !C_pool)))
+        return fail(SG_EINVAL, "sg_sweep: NULL argument");
+    if (n < 0 || warmup < 0 || reps < 1) return fail(SG_EINVAL, "sg_sweep: bad counts");
+    if (c_dtype != SG_F32 && c_dtype != SG_BF16) return fail(SG_EINVAL, "bad c_dtype");
+    DeviceGuard guard(ctx->device);
+    hipStream_t s = (hipStream_t)stream;
+    std::fill(ctx->acct_launches.begin(), ctx->acct_launches.end(), 0);
+    std::fill(ctx->acct_seconds.begin(), ctx->acct_seconds.end(), 0.0);
+    std::fill(ctx->acct_flops.begin(), ctx->acct_flops.end(), 0.0);
+    std::vector<Leaf> leaves;
+    for (int64_t i = 0; i < n; ++i) {
+        const sg_shape& sh = shapes[i];
+        if (sh.M <= 0 || sh.N <= 0 || sh.K <= 0) return fail(SG_EINVAL, "sg_sweep: empty shape");
+        Problem pr{sh.M, sh.N, sh.K, (const uint16_t*)A_pool, sh.K, (const uint16_t*)B_pool, sh.N,
+                   C_pool, sh.N, c_dtype == SG_BF16, 0};
+        int rc = make_plan(ctx, pr, mode, variant, leaves);
+        if (rc) return rc;
+        if (i == 0) {
+            size_t acc_bytes = 0;
+            rc = ensure_ws(ctx, plan_workspace(pr, leaves, &acc_bytes));
+            if (rc) return rc;
+            for (int w = 0; w < warmup; ++w)
+                for (const Leaf& L : leaves) {
+                    rc = run_leaf(pr, L, ctx->ws, acc_bytes, s);
+                    if (rc) return rc;
+                }
+        }
+        rc = time_plan(ctx, pr, leaves, reps, s, &out_sec[i], true);
+        if (rc) return rc;
+    }
+    return SG_OK;
+}
+
+extern "C" int sg_sweep_kernel_times(const sg_ctx* ctx, int64_t* launches, double* seconds,
+                                     double* flops) {
+    if (!ctx) return fail(SG_EINVAL, "NULL ctx");
+    for (int v = 0; v < kNumVariants; ++v) {
+        if (launches) launches[v] = ctx->acct_launches[v];
+        if (seconds) seconds[v] = ctx->acct_seconds[v];
+        if (flops) flops[v] = ctx->acct_flops[v];
+    }
+    return SG_OK;
+}
+
+// ---- table measurement (used by table.cpp) ----------------------------------------------------
+namespace sg {
+
+int measure_t0(sg_ctx* ctx, const std::vector<sg_shape>& order, const std::vector<int64_t>& cells,
+               const int* variants, int nvar, int c_dtype, int warmup, int reps,
+               const void* A_pool, const void* B_pool, void* C_pool, hipStream_t s,
+               std::vector<double>& T0, int64_t ncells) {
+    DeviceGuard guard(ctx->device);
+    std::vector<Leaf> leaves(1);
+    for (size_t i = 0; i < order.size(); ++i) {
+        const sg_shape& sh = order[i];
+        Problem pr{sh.M, sh.N, sh.K, (const uint16_t*)A_pool, sh.K, (const uint16_t*)B_pool, sh.N,
+                   C_pool, sh.N, c_dtype == SG_BF16, 0};
+        for (int v = 0; v < nvar; ++v) {
+            leaves[0] = Leaf{0, 0, 0, sh.M, sh.N, sh.K, sh.M, sh.N, sh.K, variants[v], true, true};
+            if (i == 0 && v == 0) {
+                size_t acc_bytes = 0;
+                int rc = ensure_ws(ctx, plan_workspace(pr, leaves, &acc_bytes));
+                if (rc) return rc;
+                for (int w = 0; w < warmup; ++w) {
+                    rc = run_leaf(pr, leaves[0], ctx->ws, acc_bytes, s);
+                    if (rc) return rc;
+                }
+            }
+            double sec = 0.0;
+            int rc = time_plan(ctx, pr, leaves, reps, s, &sec, false);
+            if (rc) return rc;
+            T0[(size_t)v * ncells + cells[i]] = sec;
+        }
+    }
+    return SG_OK;
+}
+
+}  // namespace sg

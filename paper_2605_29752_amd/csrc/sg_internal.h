@@ -1,0 +1,63 @@
+// Internal declarations shared by the smoothgemm host runtime and kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+#include <string>
+#include <vector>
+
+#include "../../include/smoothgemm.h"
+
+namespace sg {
+
+// Thread-local error message; every C entry point records its failure through this.
+int fail(int code, const std::string& msg);
+int hip_fail(hipError_t e, const char* what);
+
+#define SG_HIP(call)                                   \
+    do {                                               \
+        hipError_t e_ = (call);                        \
+        if (e_ != hipSuccess) return ::sg::hip_fail(e_, #call); \
+    } while (0)
+
+// One GEMM kernel launch of the tile family.
+//  data dims (M, N, K) bound every load and store; the launch covers (Ml, Nl) in whole tiles
+//  and runs the K loop over Kl >= K (padding: beyond K the operands read as zero).
+struct LaunchDesc {
+    int64_t M, N, K;
+    int64_t Ml, Nl, Kl;
+    const uint16_t* A; int64_t lda;
+    const uint16_t* B; int64_t ldb;
+    void* C; int64_t ldc;
+    int out_bf16;                  // 1: C is BF16, 0: FP32
+    const void* add; int64_t ldadd;
+    int add_kind;                  // 0 none, 1 FP32 addend, 2 BF16 addend (may alias C)
+};
+
+enum { ADD_NONE = 0, ADD_F32 = 1, ADD_BF16 = 2 };
+
+constexpr int kNumTiles = 7;
+constexpr int kSplitLevels = 4;               // S = 1, 2, 4, 8
+constexpr int kNumVariants = kNumTiles * kSplitLevels;
+constexpr int kBK = 64;
+
+struct TileShape { int bm, bn; };
+extern const TileShape kTiles[kNumTiles];
+
+inline int variant_tile(int v) { return v / kSplitLevels; }
+inline int variant_splits(int v) { return 1 << (v % kSplitLevels); }
+
+// Number of non-empty K splits and the K extent of each for a launch of K extent Kl.
+void split_geometry(int variant, int64_t Kl, int* splits, int64_t* k_chunk);
+// Workspace bytes the variant needs for this launch (0 when it writes C directly).
+size_t launch_workspace_bytes(int variant, const LaunchDesc& d);
+// Enqueue one launch (and, for S > 1, its reduction).  ws must hold launch_workspace_bytes.
+int launch_variant(int variant, const LaunchDesc& d, void* ws, hipStream_t stream);
+int lds_bytes_of_tile(int tile);
+
+// Device generator launcher.
+int launch_fill(uint16_t* dst, int64_t n, uint64_t seed, uint64_t stream_id, int64_t offset,
+                int kind, double scale, hipStream_t stream);
+
+}  // namespace sg

@@ -1,0 +1,146 @@
+"""The C-ABI library on the CPU: every declared symbol is exported, and the host-side logic
+(dispatch table DP, lookup, save/load, metrics) agrees with the oracle.  No GPU calls."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2605_29752_amd as sg
+from oracle import dp as odp
+from oracle import metrics as om
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    names = []
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if not fn.endswith(".h"):
+            continue
+        text = open(os.path.join(ROOT, "include", fn)).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        for m in re.finditer(r"^[A-Za-z_][\w\s\*]*?\b([a-z_][a-z0-9_]*)\s*\(", text, flags=re.M):
+            if not m.group(0).lstrip().startswith(("typedef", "#", "return")):
+                names.append(m.group(1))
+    return sorted(set(names))
+
+
+def test_library_exports_every_declared_symbol():
+    L = ctypes.CDLL(sg.LIB_PATH)
+    names = _declared_functions()
+    assert len(names) >= 20
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+    # and the binding covers every one of them
+    assert sorted(sg.declared_symbols()) == names
+
+
+def test_variant_family():
+    n = sg.num_variants()
+    assert n == 28
+    seen = set()
+    for v in range(n):
+        info = sg.variant_info(v)
+        assert info.lds_bytes <= 160 * 1024
+        seen.add((info.bm, info.bn, info.splits))
+    assert len(seen) == n
+    with pytest.raises(sg.SGError):
+        sg.variant_info(n)
+
+
+@pytest.mark.parametrize("shape", [(2, 3, 4), (5, 5, 5), (6, 4, 7), (8, 8, 8)])
+def test_table_dp_matches_oracle(shape):
+    rng = np.random.default_rng(sum(shape))
+    nv = 3
+    T0 = rng.uniform(1.0, 10.0, size=(nv,) + shape)
+    t = sg.Table.from_t0(128, *shape, T0, [0, 3, 6])
+    best = T0.min(axis=0)
+    T1, T2, act, arg = odp.tables(best)
+    assert np.array_equal(t.values(0), best)
+    assert np.array_equal(t.values(1), T1)
+    assert np.array_equal(t.values(2), T2)
+    assert np.array_equal(t.values(3), T0)
+    vids = np.array([0, 3, 6])[T0.argmin(axis=0)]
+    for cell in np.ndindex(shape):
+        M, N, K = [(c + 1) * 128 for c in cell]
+        r = t.lookup(M, N, K)
+        assert r["action"] == act[cell] and r["arg"] == arg[cell], cell
+        if r["action"] == sg.ACT_AS_IS:
+            assert r["variant"] == vids[cell]
+        if r["action"] == sg.ACT_PAD:
+            assert r["variant"] == vids[np.unravel_index(arg[cell], shape)]
+        assert t.plan_leaves(M, N, K) == len(odp.plan_leaves(shape, act, arg, cell))
+
+
+def test_table_lookup_off_grid_and_range():
+    T0 = np.random.default_rng(1).uniform(1, 2, size=(1, 4, 4, 4))
+    t = sg.Table.from_t0(128, 4, 4, 4, T0, [3])
+    assert t.lookup(1, 1, 1)["t0"] == T0[0, 0, 0, 0]
+    assert t.lookup(129, 128, 257)["t0"] == T0[0, 1, 0, 2]
+    assert t.lookup(512, 512, 512)["t0"] == T0[0, 3, 3, 3]
+    with pytest.raises(sg.SGError) as e:
+        t.lookup(513, 1, 1)
+    assert e.value.code == sg.SG_ERANGE
+    with pytest.raises(sg.SGError):
+        t.lookup(0, 5, 5)
+
+
+def test_table_rejects_bad_t0():
+    T0 = np.ones((1, 2, 2, 2))
+    T0[0, 1, 1, 1] = np.nan
+    with pytest.raises(sg.SGError):
+        sg.Table.from_t0(128, 2, 2, 2, T0, [0])
+    with pytest.raises(sg.SGError):
+        sg.Table.from_t0(128, 2, 2, 2, np.ones((1, 2, 2, 2)), [99])
+    with pytest.raises(sg.SGError):
+        sg.Table.from_t0(0, 2, 2, 2, np.ones((1, 2, 2, 2)), [0])
+
+
+def test_table_save_load_roundtrip(tmp_path):
+    T0 = np.random.default_rng(2).uniform(1, 2, size=(2, 3, 4, 5))
+    t = sg.Table.from_t0(64, 3, 4, 5, T0, [1, 2])
+    p = str(tmp_path / "t.sgt")
+    t.save(p)
+    t2 = sg.Table.load(p, force=True)
+    for w in range(4):
+        assert np.array_equal(t.values(w), t2.values(w))
+    assert t2.grid() == (64, 3, 4, 5) and t2.variants() == [1, 2]
+    open(p, "r+b").write(b"XXXX")
+    with pytest.raises(sg.SGError) as e:
+        sg.Table.load(p, force=True)
+    assert e.value.code == sg.SG_EIO
+
+
+def test_metrics_match_oracle():
+    rng = np.random.default_rng(3)
+    T = rng.uniform(0, 100, size=(5, 6, 7))
+    got = sg.landscape_stats(T)
+    want = om.aggregate_3d(T)
+    for k in ("mean", "peak", "roughness_m", "roughness_n", "roughness_k", "roughness_3d"):
+        assert got[k] == pytest.approx(want[k], rel=1e-12), k
+    v = rng.uniform(0, 10, size=33)
+    assert sg.roughness(v) == pytest.approx(om.roughness(v), rel=1e-12)
+    assert np.isnan(sg.roughness([1.0]))
+    with pytest.raises(sg.SGError):
+        sg.landscape_stats(np.zeros((1, 3, 3)))
+
+
+def test_ideal_landscape_through_library():
+    sizes = list(range(128, 4097, 128))
+    L = np.array([[om.ideal_tflops(m, n, 108.2, 20, 256) for n in sizes] for m in sizes])
+    # a K axis of two identical slices keeps the per-slice N roughness
+    st = sg.landscape_stats(np.stack([L, L], axis=2))
+    assert abs(st["mean"] - 97.2) <= 0.05 and abs(st["roughness_n"] - 2.0) <= 0.05
+
+
+def test_synthetic_plans_cover_every_action():
+    """The GPU plan-execution tests rely on these synthetic tables producing every action."""
+    import sys
+    sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+    from test_gpu_dp import _random_table
+    for seed, shape, variants in [(1, (4, 4, 5), [3, 6, 9, 26]), (2, (5, 5, 5), [3, 6, 10, 25])]:
+        t, _ = _random_table(seed, shape, 64, variants)
+        acts = {t.lookup(*[(c + 1) * 64 for c in cell])["action"] for cell in np.ndindex(shape)}
+        assert acts == {0, 1, 2, 3, 4}
