@@ -1,0 +1,267 @@
+#!/usr/bin/env python
+"""Landscape benchmark of the smoothed BF16 NN GEMM stack on one MI355X.
+
+Workload: every (M, N, K) in {128, 256, ..., 4096}^3 (32,768 shapes), BF16 inputs drawn
+uniform[-1, 1] (seeded), FP32 accumulation, BF16 output.  Operands are views of one resident
+4096 x 4096 pool per operand (A is the first M*K elements with lda = K, B the first K*N with
+ldb = N).
+
+Set-up (untimed): measure T0 for every variant of the tile family at every shape (randomized
+order, warm-ups, one discarded and `reps` timed launches per shape), then build the dispatch
+table (best-of-N, T1 pad, T2 split + pad).
+Timed step: one pass over all 32,768 shapes executed through the dispatch table (each shape:
+one untimed run, then `reps` timed runs of its plan), in the same randomized order.
+
+Prints one JSON line: mean TFLOPs over the 32,768 shapes of the executed smoothed stack, with
+roughness and the other stacks (plain single tile, best-of-N, DP as predicted by the table)
+beside it, the roofline of the dominant kernel and the FP64 oracle's CPU rate.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_BF16_TFLOPS = 2516.6       # MI355X dense BF16 MFMA (256 CUs x 4096 FLOP/clk x 2.4 GHz)
+DEFAULT_VARIANTS = "0,4,8,12,13,14,16,17,18,24,26,27"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def stack_stats(sg, sec, sizes):
+    """Per-shape seconds [nM, nN, nK] -> mean/peak/roughness (3-D and the K = max slice)."""
+    M = sizes[:, None, None]
+    N = sizes[None, :, None]
+    K = sizes[None, None, :]
+    tf = 2.0 * M * N * K / (sec * 1e12)
+    st = sg.landscape_stats(tf)
+    sl = tf[:, :, -1]
+    slice_rough = float(np.mean([sg.roughness(row) for row in sl]))
+    return {"mean_tflops": st["mean"], "peak_tflops": st["peak"],
+            "roughness_3d": st["roughness_3d"], "roughness_n": st["roughness_n"],
+            "roughness_m": st["roughness_m"], "roughness_k": st["roughness_k"],
+            "slice_k%d_mean" % int(sizes[-1]): float(sl.mean()),
+            "slice_k%d_roughness_n" % int(sizes[-1]): slice_rough,
+            "frac_of_peak_mean": st["mean"] / PEAK_BF16_TFLOPS}
+
+
+def cpu_baseline(seconds_budget: float, seed: int):
+    """The FP64 oracle, untuned, on a bounded seeded sample of the grid's smaller shapes."""
+    import oracle
+    import synth
+    rng = np.random.default_rng(seed)
+    sizes = np.arange(128, 4097, 128)
+    # operands are the same pool views the GPU uses (first M*K / K*N elements of the pools)
+    cand = [(m, n, k) for m in sizes for n in sizes for k in sizes if m * n * k <= (1 << 25)]
+    order = rng.permutation(len(cand))
+    shapes, flops, secs = [], [], []
+    t_start = time.perf_counter()
+    a_pool = synth.uniform_bf16(seed, synth.STREAM_A, 1, 1 << 20).ravel()
+    b_pool = synth.uniform_bf16(seed, synth.STREAM_B, 1, 1 << 20).ravel()
+    for idx in order:
+        m, n, k = (int(x) for x in cand[idx])
+        A = a_pool[:m * k].reshape(m, k)
+        B = b_pool[:k * n].reshape(k, n)
+        t0 = time.perf_counter()
+        oracle.gemm_f64(A, B, want_d=False)
+        dt = time.perf_counter() - t0
+        shapes.append((m, n, k))
+        flops.append(2.0 * m * n * k)
+        secs.append(dt)
+        if time.perf_counter() - t_start > seconds_budget:
+            break
+    tf = np.array(flops) / np.array(secs) / 1e12
+    return {"value": float(tf.mean()), "unit": "TFLOPs", "cores": 1, "kind": "oracle",
+            "sample": "%d seeded grid shapes with M*N*K <= 2^25 (e.g. %s), plain FP64 C loop, "
+                      "1 thread, %.1f s total; value = mean over the sample of 2MNK/t"
+                      % (len(shapes), "x".join(map(str, shapes[0])), float(np.sum(secs))),
+            "aggregate_tflops": float(np.sum(flops) / np.sum(secs) / 1e12)}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2, help="timed passes over the sweep")
+    ap.add_argument("--warmup", type=int, default=1, help="untimed passes before timing")
+    ap.add_argument("--reps", type=int, default=5, help="timed runs per shape (one more is discarded)")
+    ap.add_argument("--shape-warmup", type=int, default=5, help="warm-up runs before a pass")
+    ap.add_argument("--step", type=int, default=128, help="grid step")
+    ap.add_argument("--n", type=int, default=32, help="grid points per axis")
+    ap.add_argument("--variants", default=DEFAULT_VARIANTS)
+    ap.add_argument("--plain-variant", type=int, default=0)
+    ap.add_argument("--table", default=None, help="load this table instead of measuring one")
+    ap.add_argument("--save-table", default=None)
+    ap.add_argument("--seed", type=int, default=2)
+    ap.add_argument("--order-seed", type=int, default=11)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--dump", default=None, help="write per-shape arrays (.npz) here")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: the landscape sweep, its dispatch table and every kernel "
+              "run on a single MI355X; runs on %d GPUs are not part of this build" % max(args.gpus, world),
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2605_29752_amd as sg
+
+    assert torch.cuda.is_available(), "bench.py needs the GPU"
+    dev = torch.cuda.current_device()
+    props = torch.cuda.get_device_properties(dev)
+    ctx = sg.Context(dev)
+    ctx.set_plain_variant(args.plain_variant)
+    stream = torch.cuda.current_stream()
+
+    n, step = args.n, args.step
+    sizes = np.arange(1, n + 1, dtype=np.float64) * step
+    maxdim = n * step
+    pool = maxdim * maxdim
+    A = torch.empty(pool, dtype=torch.bfloat16, device="cuda")
+    B = torch.empty(pool, dtype=torch.bfloat16, device="cuda")
+    C = torch.empty(pool, dtype=torch.bfloat16, device="cuda")
+    sg.fill_bf16(A, args.seed, 0)           # same bits as the host generator (tested)
+    sg.fill_bf16(B, args.seed, 1)
+    torch.cuda.synchronize()
+
+    variants = [int(v) for v in args.variants.split(",")]
+    if args.plain_variant not in variants:
+        variants = [args.plain_variant] + variants
+    t_tab = time.perf_counter()
+    if args.table:
+        table = sg.Table.load(args.table)
+        variants = table.variants()
+    else:
+        log("measuring T0: %d variants x %d shapes" % (len(variants), n ** 3))
+        table = ctx.build_table(step, n, n, n, variants, A, B, C, c_dtype=sg.BF16,
+                                warmup=args.shape_warmup, reps=args.reps,
+                                order_seed=args.order_seed, stream=stream)
+        if args.save_table:
+            table.save(args.save_table)
+    table_s = time.perf_counter() - t_tab
+    log("table ready in %.1f s" % table_s)
+    ctx.set_table(table)
+
+    T0all = table.values(3)
+    T0best, T1, T2 = table.values(0), table.values(1), table.values(2)
+    plain_row = variants.index(args.plain_variant)
+
+    rng = np.random.default_rng(args.order_seed)
+    cells = rng.permutation(n ** 3)
+    idx = np.array(np.unravel_index(cells, (n, n, n))).T
+    shapes = [(int((i + 1) * step), int((j + 1) * step), int((k + 1) * step)) for i, j, k in idx]
+
+    def one_pass():
+        return ctx.sweep(shapes, A, B, C, mode=sg.MODE_DP, c_dtype=sg.BF16,
+                         warmup=args.shape_warmup, reps=args.reps, stream=stream)
+
+    for w in range(args.warmup):
+        log("warm-up pass %d" % w)
+        one_pass()
+    torch.cuda.synchronize()
+    passes = []
+    launches = np.zeros(sg.num_variants(), dtype=np.int64)
+    ksec = np.zeros(sg.num_variants())
+    kflops = np.zeros(sg.num_variants())
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        sec = one_pass()
+        la, se, fl = ctx.kernel_times()
+        launches += la
+        ksec += se
+        kflops += fl
+        passes.append(sec)
+        log("timed pass %d done" % s)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_per_step = wall / args.steps * 1e3
+
+    exec_sec = np.zeros(n ** 3)
+    exec_sec[cells] = np.mean(passes, axis=0)
+    exec_sec = exec_sec.reshape(n, n, n)
+
+    stacks = {
+        "plain_%s" % sg.variant_info(args.plain_variant).name: stack_stats(sg, T0all[plain_row], sizes),
+        "best_of_%d" % len(variants): stack_stats(sg, T0best, sizes),
+        "dp_pad_table": stack_stats(sg, T1, sizes),
+        "dp_split_pad_table": stack_stats(sg, T2, sizes),
+        "dp_split_pad_executed": stack_stats(sg, exec_sec, sizes),
+    }
+    # best single variant by mean over the sweep
+    means = [stack_stats(sg, T0all[r], sizes)["mean_tflops"] for r in range(len(variants))]
+    best_single = variants[int(np.argmax(means))]
+    stacks["best_single_%s" % sg.variant_info(best_single).name] = \
+        stack_stats(sg, T0all[variants.index(best_single)], sizes)
+
+    dom = int(np.argmax(ksec))
+    achieved = kflops[dom] / ksec[dom] / 1e12
+    ex = stacks["dp_split_pad_executed"]
+    plain = stacks["plain_%s" % sg.variant_info(args.plain_variant).name]
+
+    actions = {}
+    for c in range(n ** 3):
+        i, j, k = np.unravel_index(c, (n, n, n))
+        a = table.lookup(int((i + 1) * step), int((j + 1) * step), int((k + 1) * step))["action"]
+        actions[a] = actions.get(a, 0) + 1
+    names = {0: "as_is", 1: "pad", 2: "split_m", 3: "split_n", 4: "split_k"}
+
+    result = {
+        "metric": "mean BF16 TFLOPs + roughness over 32,768-shape sweep; served p50/p99 latency",
+        "value": ex["mean_tflops"],
+        "unit": "TFLOPs",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16",
+        "data": "synthetic",
+        "config": {"workload": "BF16 NN GEMM landscape sweep, (M,N,K) in {%d..%d}^3 step %d "
+                               "(%d shapes), uniform[-1,1] BF16 inputs, FP32 accumulate, BF16 "
+                               "output, executed through best-of-N + DP pad/split dispatch table"
+                               % (step, maxdim, step, n ** 3),
+                   "shapes": n ** 3, "variants": [sg.variant_info(v).name for v in variants],
+                   "reps_per_shape": args.reps, "order": "randomized (seed %d)" % args.order_seed},
+        "roughness_3d": ex["roughness_3d"],
+        "roughness_slice_k%d" % maxdim: ex["slice_k%d_roughness_n" % maxdim],
+        "peak_tflops": ex["peak_tflops"],
+        "frac_of_bf16_peak_mean": ex["mean_tflops"] / PEAK_BF16_TFLOPS,
+        "gain_vs_plain": {"mean": ex["mean_tflops"] / plain["mean_tflops"] - 1.0,
+                          "roughness_3d": ex["roughness_3d"] / plain["roughness_3d"] - 1.0,
+                          "roughness_slice": ex["slice_k%d_roughness_n" % maxdim] /
+                          plain["slice_k%d_roughness_n" % maxdim] - 1.0},
+        "stacks": stacks,
+        "dp_actions": {names[a]: c / n ** 3 for a, c in sorted(actions.items())},
+        "table_build_s": table_s,
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_BF16_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_BF16_TFLOPS, "traffic": None,
+                     "kernel": "sg_gemm_tile " + sg.variant_info(dom).name,
+                     "launches": int(launches[dom]),
+                     "avg_launch_us": ksec[dom] / max(launches[dom], 1) * 1e6,
+                     "flop_per_launch": kflops[dom] / max(launches[dom], 1)},
+        "device": props.name,
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline")
+        result["cpu_baseline"] = cpu_baseline(args.cpu_seconds, args.seed)
+    if args.dump:
+        np.savez_compressed(args.dump, sizes=sizes, T0=T0all, T0best=T0best, T1=T1, T2=T2,
+                            executed=exec_sec, variants=np.array(variants))
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

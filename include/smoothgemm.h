@@ -111,17 +111,18 @@ int sg_landscape_stats(const double* tflops, int nM, int nN, int nK, sg_stats* o
  * Runs the n shapes in the order given (shuffle them for the randomized protocol) with
  * `warmup` untimed runs of the first shape up front, then per shape one untimed run and `reps`
  * timed runs; out_sec[i] = mean seconds of one run of shape i.  Each run is one complete
- * execution in `mode` (a DP run may be several kernel launches).  Each shape views the pools as
- * A = first M*K elements (lda = K), B = first K*N (ldb = N), C = first M*N (ldc = N): pools must
- * hold at least max(M*K), max(K*N), max(M*N) elements.  out_launch_sec / out_launches, if not
- * NULL, receive per-shape summed kernel-launch seconds of the dominant variant (see
- * sg_sweep_kernel_times). */
+ * execution in `mode` (a DP run may be several kernel launches).  A run's time is the sum of
+ * its kernels' execution times, each taken from the start/end timestamps of its own dispatch
+ * (the kernel time a profiler reports; host launch gaps are excluded).  Each shape views the
+ * pools as A = first M*K elements (lda = K), B = first K*N (ldb = N), C = first M*N (ldc = N):
+ * pools must hold at least max(M*K), max(K*N), max(M*N) elements.  Per-variant totals of the
+ * timed runs are kept in the context (sg_sweep_kernel_times). */
 typedef struct sg_shape { int64_t M, N, K; } sg_shape;
 int sg_sweep(sg_ctx* ctx, const sg_shape* shapes, int64_t n, int mode, int variant, int c_dtype,
              int warmup, int reps, const void* A_pool, const void* B_pool, void* C_pool,
              double* out_sec, void* stream);
 /* Per-variant launch accounting of the most recent sg_sweep on this context: for variant v,
- * launches[v] kernel launches took seconds[v] in total (event to event, timed runs only) and
+ * launches[v] kernel launches took seconds[v] of kernel execution in total (timed runs only) and
  * did flops[v] algorithmic FLOP (2 M N K of the data shape of each launch). Arrays hold
  * sg_num_variants() entries. */
 int sg_sweep_kernel_times(const sg_ctx* ctx, int64_t* launches, double* seconds, double* flops);
@@ -175,6 +176,114 @@ int sg_table_save(const sg_table* t, const char* path);
 int sg_table_load(const char* path, int force, sg_table** out);
 /* Borrow the table for SG_MODE_DEFAULT / BEST / DP calls (NULL clears). */
 int sg_ctx_set_table(sg_ctx* ctx, const sg_table* t);
+
+/* ---- grouped batching: many independent GEMMs in one persistent launch -------------------
+ * One problem per entry: device pointers, row-major, the same conventions as sg_gemm_args
+ * (beta = 0; all problems share c_dtype).  A plan uploads the descriptors once (device-resident,
+ * owned by the plan) and fixes the tile shape and work order; sg_group_plan_launch enqueues one
+ * persistent kernel that drains a queue of every problem's tiles.  Launches of one plan must
+ * not overlap each other (they share the plan's queue counters); launches of different plans
+ * may.  The caller owns A, B, C of every problem and keeps them alive while launches are
+ * queued. */
+typedef struct sg_problem {
+    int64_t M, N, K;
+    const void* A; int64_t lda;
+    const void* B; int64_t ldb;
+    void* C;       int64_t ldc;
+} sg_problem;
+typedef struct sg_group_cfg {
+    int tile;       /* tile shape index 0..6: 256x256, 256x128, 128x256, 128x128, 128x64, 64x128, 64x64 */
+    int grid_wgs;   /* resident work-groups; 0 = as many as the occupancy allows on every CU */
+    int order;      /* 0: longest K first (greedy longest-processing-time), 1: as given */
+} sg_group_cfg;
+typedef struct sg_group_plan sg_group_plan;
+/* cfg == NULL autotunes: every tile shape is timed on this group (one warm-up, best of three)
+ * and the fastest kept.  Synchronises `stream`. */
+int sg_group_plan_create(sg_ctx* ctx, int G, const sg_problem* probs, int c_dtype,
+                         const sg_group_cfg* cfg, void* stream, sg_group_plan** out);
+int sg_group_plan_launch(sg_group_plan* plan, void* stream);
+/* Replace the problems (same count).  Returns SG_EAGAIN when the tile count changed: graphs
+ * that captured this plan must then be captured again. */
+int sg_group_plan_update(sg_group_plan* plan, const sg_problem* probs, void* stream);
+int sg_group_plan_info(const sg_group_plan* plan, sg_group_cfg* cfg, int* total_tiles, int* grid,
+                       double* flops);
+int sg_group_plan_destroy(sg_group_plan* plan);
+/* One-shot form: plan (cfg NULL = tile 128x128), launch, wait, free. */
+int sg_gemm_grouped(sg_ctx* ctx, int G, const sg_problem* probs, int c_dtype,
+                    const sg_group_cfg* cfg, void* stream);
+
+/* hipGraph of n grouped launches in sequence (captured on `stream`, which must not be NULL).
+ * Replays reuse the plans' device descriptors: update them with sg_group_plan_update. */
+typedef struct sg_graph sg_graph;
+int sg_graph_capture_groups(sg_group_plan* const* plans, int n, void* stream, sg_graph** out);
+int sg_graph_launch(sg_graph* graph, void* stream);
+int sg_graph_destroy(sg_graph* graph);
+
+/* ---- serving: continuous batching of GEMM requests ---------------------------------------
+ * Requests C = A * B_w (B_w one of n_weights shared, device-resident weights; BF16 output) are
+ * submitted at any time from any thread.  A worker thread admits pending requests, oldest
+ * first, while their A (M x K) and C (M x N) fit in an HBM budget carved from one device
+ * allocation; stages each admitted request's A (copied from a resident pool of N(0, a_scale)
+ * activations at a per-request offset derived from (seed, id)); and launches the admitted
+ * requests as one grouped kernel on any free stream slot, so new work overlaps running work.
+ * SG_SERVE_PER_REQUEST launches every request on its own (the per-call baseline).  Times are
+ * seconds on the server's clock (sg_server_now).  The caller owns the weights and keeps them
+ * alive for the server's lifetime; the server owns request memory. */
+#define SG_SERVE_GROUPED      0
+#define SG_SERVE_PER_REQUEST  1
+typedef struct sg_weight { int64_t K, N; const void* B; int64_t ldb; } sg_weight;
+typedef struct sg_server_cfg {
+    size_t hbm_budget;          /* device bytes for request A and C (>= 1 MiB)                  */
+    int max_inflight;           /* stream slots, 1..16                                           */
+    int max_group;              /* requests per grouped launch, 1..4096                          */
+    int queue_cap;              /* pending requests before submit returns SG_EAGAIN              */
+    int mode;                   /* SG_SERVE_GROUPED or SG_SERVE_PER_REQUEST                      */
+    int tile;                   /* tile shape index 0..6 (per-request mode: the same tile, S = 1) */
+    int keep_results;           /* 1: C stays allocated until sg_server_release                  */
+    int n_weights;
+    const sg_weight* weights;   /* copied at creation                                            */
+    int64_t max_m;              /* largest request M                                             */
+    uint64_t seed;              /* activation pool and per-request offsets                       */
+    double a_scale;             /* activation standard deviation                                 */
+} sg_server_cfg;
+typedef struct sg_request { uint64_t id; int64_t M; int weight; } sg_request;
+typedef struct sg_completion {
+    uint64_t ticket, id;
+    int64_t M, N, K;
+    int weight;
+    int status;                 /* SG_OK or the failure code                                     */
+    int64_t a_offset;           /* element offset of A in the activation pool                    */
+    double t_arrival, t_admit, t_launch, t_done;
+    const void* A;              /* device; valid until release when keep_results, else NULL      */
+    const void* C;
+} sg_completion;
+typedef struct sg_server_stats {
+    int64_t submitted, completed, failed, launches, pending;
+    double flops, bytes_in_use, peak_bytes;
+} sg_server_stats;
+typedef struct sg_server sg_server;
+int sg_server_create(sg_ctx* ctx, const sg_server_cfg* cfg, sg_server** out);
+int sg_server_now(sg_server* server, double* t);
+/* Non-blocking.  arrival_s < 0 stamps the current time.  SG_EAGAIN when the queue is full;
+ * SG_EINVAL for an M or weight out of range or a request that can never fit the budget. */
+int sg_server_submit(sg_server* server, const sg_request* req, double arrival_s, uint64_t* ticket);
+/* Move up to max finished requests (oldest first) into out; *n receives the count. */
+int sg_server_poll(sg_server* server, sg_completion* out, int max, int* n);
+int sg_server_release(sg_server* server, uint64_t ticket);
+/* Wait until every submitted request has finished (SG_EAGAIN after timeout_s). */
+int sg_server_drain(sg_server* server, double timeout_s);
+int sg_server_stats_get(sg_server* server, sg_server_stats* st);
+int sg_server_destroy(sg_server* server);
+
+/* Open-loop load: Poisson arrivals at `rate` per second for duration_s, M = clamp(round(
+ * exp(U(0, ln max_m))), 1, max_m), weight uniform; waits for the drain and reports requests
+ * that arrived after warmup_s: nearest-rank p50 / p99 of (done - arrival), throughput. */
+typedef struct sg_serve_report {
+    int64_t offered, rejected, failed, measured, launches;
+    double window_s, req_per_s, tflops, p50_ms, p99_ms, mean_ms, peak_bytes;
+} sg_serve_report;
+int sg_serve_poisson(sg_server* server, double rate, double duration_s, double warmup_s,
+                     uint64_t seed, int64_t max_m, sg_serve_report* rep);
 
 /* ---- device operand generator (the seeded counter generator, on the GPU) ---------------------
  * Element idx of stream `stream` under `seed`: SplitMix64 word

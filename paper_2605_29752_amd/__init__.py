@@ -90,7 +90,69 @@ _SIGS = {
     "sg_table_save": (_i32, [_p, ctypes.c_char_p]),
     "sg_table_load": (_i32, [ctypes.c_char_p, _i32, ctypes.POINTER(_p)]),
     "sg_fill_bf16": (_i32, [_p, _i64, ctypes.c_uint64, ctypes.c_uint64, _i64, _i32, _d, _p]),
+    "sg_group_plan_create": (_i32, [_p, _i32, _p, _i32, _p, _p, ctypes.POINTER(_p)]),
+    "sg_group_plan_launch": (_i32, [_p, _p]),
+    "sg_group_plan_update": (_i32, [_p, _p, _p]),
+    "sg_group_plan_info": (_i32, [_p, _p, ctypes.POINTER(_i32), ctypes.POINTER(_i32), ctypes.POINTER(_d)]),
+    "sg_group_plan_destroy": (_i32, [_p]),
+    "sg_gemm_grouped": (_i32, [_p, _i32, _p, _i32, _p, _p]),
+    "sg_graph_capture_groups": (_i32, [_p, _i32, _p, ctypes.POINTER(_p)]),
+    "sg_graph_launch": (_i32, [_p, _p]),
+    "sg_graph_destroy": (_i32, [_p]),
+    "sg_server_create": (_i32, [_p, _p, ctypes.POINTER(_p)]),
+    "sg_server_now": (_i32, [_p, ctypes.POINTER(_d)]),
+    "sg_server_submit": (_i32, [_p, _p, _d, ctypes.POINTER(ctypes.c_uint64)]),
+    "sg_server_poll": (_i32, [_p, _p, _i32, ctypes.POINTER(_i32)]),
+    "sg_server_release": (_i32, [_p, ctypes.c_uint64]),
+    "sg_server_drain": (_i32, [_p, _d]),
+    "sg_server_stats_get": (_i32, [_p, _p]),
+    "sg_server_destroy": (_i32, [_p]),
+    "sg_serve_poisson": (_i32, [_p, _d, _d, _d, ctypes.c_uint64, _i64, _p]),
 }
+
+SERVE_GROUPED, SERVE_PER_REQUEST = 0, 1
+
+
+class sg_weight(ctypes.Structure):
+    _fields_ = [("K", _i64), ("N", _i64), ("B", _p), ("ldb", _i64)]
+
+
+class sg_server_cfg(ctypes.Structure):
+    _fields_ = [("hbm_budget", ctypes.c_size_t), ("max_inflight", _i32), ("max_group", _i32),
+                ("queue_cap", _i32), ("mode", _i32), ("tile", _i32), ("keep_results", _i32),
+                ("n_weights", _i32), ("weights", ctypes.POINTER(sg_weight)), ("max_m", _i64),
+                ("seed", ctypes.c_uint64), ("a_scale", _d)]
+
+
+class sg_request(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_uint64), ("M", _i64), ("weight", _i32)]
+
+
+class sg_completion(ctypes.Structure):
+    _fields_ = [("ticket", ctypes.c_uint64), ("id", ctypes.c_uint64), ("M", _i64), ("N", _i64),
+                ("K", _i64), ("weight", _i32), ("status", _i32), ("a_offset", _i64),
+                ("t_arrival", _d), ("t_admit", _d), ("t_launch", _d), ("t_done", _d),
+                ("A", _p), ("C", _p)]
+
+
+class sg_server_stats(ctypes.Structure):
+    _fields_ = [("submitted", _i64), ("completed", _i64), ("failed", _i64), ("launches", _i64),
+                ("pending", _i64), ("flops", _d), ("bytes_in_use", _d), ("peak_bytes", _d)]
+
+
+class sg_serve_report(ctypes.Structure):
+    _fields_ = [("offered", _i64), ("rejected", _i64), ("failed", _i64), ("measured", _i64),
+                ("launches", _i64), ("window_s", _d), ("req_per_s", _d), ("tflops", _d),
+                ("p50_ms", _d), ("p99_ms", _d), ("mean_ms", _d), ("peak_bytes", _d)]
+
+
+class sg_problem(ctypes.Structure):
+    _fields_ = [("M", _i64), ("N", _i64), ("K", _i64), ("A", _p), ("lda", _i64), ("B", _p),
+                ("ldb", _i64), ("C", _p), ("ldc", _i64)]
+
+
+class sg_group_cfg(ctypes.Structure):
+    _fields_ = [("tile", _i32), ("grid_wgs", _i32), ("order", _i32)]
 
 _lib = None
 
@@ -321,6 +383,139 @@ class Context:
                                    reps, order_seed, A_pool.data_ptr(), B_pool.data_ptr(),
                                    C_pool.data_ptr(), _stream_ptr(stream), ctypes.byref(h)))
         return Table(h.value)
+
+
+def _problems(probs):
+    """[(M, N, K, A_ptr, lda, B_ptr, ldb, C_ptr, ldc), ...] -> ctypes array."""
+    arr = (sg_problem * len(probs))()
+    for i, p in enumerate(probs):
+        arr[i] = sg_problem(*[int(x) for x in p])
+    return arr
+
+
+class GroupPlan:
+    """A grouped launch: device-resident descriptors, fixed tile shape and work order."""
+
+    def __init__(self, ctx: "Context", probs, c_dtype: int = BF16, tile: Optional[int] = None,
+                 grid_wgs: int = 0, order: int = 0, stream=None):
+        self._probs = _problems(probs)
+        cfg = None if tile is None else ctypes.byref(sg_group_cfg(tile, grid_wgs, order))
+        h = ctypes.c_void_p()
+        check(lib().sg_group_plan_create(ctx.handle, len(probs), self._probs, c_dtype, cfg,
+                                         _stream_ptr(stream), ctypes.byref(h)))
+        self.handle = h
+
+    def launch(self, stream=None):
+        check(lib().sg_group_plan_launch(self.handle, _stream_ptr(stream)))
+
+    def update(self, probs, stream=None):
+        self._probs = _problems(probs)
+        check(lib().sg_group_plan_update(self.handle, self._probs, _stream_ptr(stream)))
+
+    def info(self) -> dict:
+        cfg = sg_group_cfg()
+        tiles, grid, flops = ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
+        check(lib().sg_group_plan_info(self.handle, ctypes.byref(cfg), ctypes.byref(tiles),
+                                       ctypes.byref(grid), ctypes.byref(flops)))
+        return {"tile": cfg.tile, "grid_wgs": grid.value, "order": cfg.order,
+                "total_tiles": tiles.value, "flops": flops.value}
+
+    def close(self):
+        if getattr(self, "handle", None) and self.handle.value and _lib is not None:
+            _lib.sg_group_plan_destroy(self.handle)
+            self.handle = ctypes.c_void_p(0)
+
+    def __del__(self):
+        self.close()
+
+
+class Graph:
+    """hipGraph holding a sequence of grouped launches."""
+
+    def __init__(self, plans, stream):
+        arr = (ctypes.c_void_p * len(plans))(*[p.handle.value for p in plans])
+        h = ctypes.c_void_p()
+        check(lib().sg_graph_capture_groups(arr, len(plans), _stream_ptr(stream), ctypes.byref(h)))
+        self.handle = h
+        self._plans = list(plans)
+
+    def launch(self, stream=None):
+        check(lib().sg_graph_launch(self.handle, _stream_ptr(stream)))
+
+    def close(self):
+        if getattr(self, "handle", None) and self.handle.value and _lib is not None:
+            _lib.sg_graph_destroy(self.handle)
+            self.handle = ctypes.c_void_p(0)
+
+    def __del__(self):
+        self.close()
+
+
+class Server:
+    """Continuous-batching GEMM server (worker thread inside the library)."""
+
+    def __init__(self, ctx: "Context", weights, *, hbm_budget: int, max_inflight: int = 4,
+                 max_group: int = 64, queue_cap: int = 1 << 20, mode: int = SERVE_GROUPED,
+                 tile: int = 3, keep_results: bool = False, max_m: int = 8192, seed: int = 5,
+                 a_scale: float = 0.02):
+        """weights: [(K, N, B_ptr, ldb), ...] device-resident BF16 matrices."""
+        self._w = (sg_weight * len(weights))(*[sg_weight(*[int(x) for x in w]) for w in weights])
+        cfg = sg_server_cfg(hbm_budget, max_inflight, max_group, queue_cap, mode, tile,
+                            1 if keep_results else 0, len(weights), self._w, max_m, seed, a_scale)
+        h = ctypes.c_void_p()
+        check(lib().sg_server_create(ctx.handle, ctypes.byref(cfg), ctypes.byref(h)))
+        self.handle = h
+
+    def now(self) -> float:
+        t = ctypes.c_double()
+        check(lib().sg_server_now(self.handle, ctypes.byref(t)))
+        return t.value
+
+    def submit(self, req_id: int, M: int, weight: int, arrival: float = -1.0) -> int:
+        r = sg_request(req_id, M, weight)
+        tk = ctypes.c_uint64()
+        check(lib().sg_server_submit(self.handle, ctypes.byref(r), arrival, ctypes.byref(tk)))
+        return tk.value
+
+    def poll(self, max_n: int = 1024):
+        buf = (sg_completion * max_n)()
+        n = ctypes.c_int()
+        check(lib().sg_server_poll(self.handle, buf, max_n, ctypes.byref(n)))
+        return [buf[i] for i in range(n.value)]
+
+    def release(self, ticket: int):
+        check(lib().sg_server_release(self.handle, ticket))
+
+    def drain(self, timeout: float = 600.0):
+        check(lib().sg_server_drain(self.handle, timeout))
+
+    def stats(self) -> dict:
+        st = sg_server_stats()
+        check(lib().sg_server_stats_get(self.handle, ctypes.byref(st)))
+        return {f: getattr(st, f) for f, _ in sg_server_stats._fields_}
+
+    def serve_poisson(self, rate: float, duration: float, warmup: float, seed: int,
+                      max_m: int = 8192) -> dict:
+        rep = sg_serve_report()
+        check(lib().sg_serve_poisson(self.handle, rate, duration, warmup, seed, max_m,
+                                     ctypes.byref(rep)))
+        return {f: getattr(rep, f) for f, _ in sg_serve_report._fields_}
+
+    def close(self):
+        if getattr(self, "handle", None) and self.handle.value and _lib is not None:
+            _lib.sg_server_destroy(self.handle)
+            self.handle = ctypes.c_void_p(0)
+
+    def __del__(self):
+        self.close()
+
+
+def gemm_grouped(ctx: "Context", probs, c_dtype: int = BF16, tile: int = 3, stream=None):
+    """One-shot grouped launch (plan, launch, wait, free)."""
+    arr = _problems(probs)
+    cfg = sg_group_cfg(tile, 0, 0)
+    check(lib().sg_gemm_grouped(ctx.handle, len(probs), arr, c_dtype, ctypes.byref(cfg),
+                                _stream_ptr(stream)))
 
 
 def gemm_bf16_nn(M: int, N: int, K: int, A, B, C):

@@ -1,0 +1,354 @@
+// Persistent grouped BF16 NN GEMM: many independent problems of uneven shape in one launch.
+//
+// The grid holds as many work-groups as the device keeps resident at once.  Each work-group
+// takes the next tile from a global work queue (an atomic counter), finds its problem by binary
+// search over the per-problem tile prefix sums, and runs the same tile body as the per-call
+// kernel, so every output element is computed exactly as a per-call launch of the same tile
+// shape computes it.  Problems are ordered longest-K first (largest tile cost first), so the
+// greedy queue behaves like longest-processing-time scheduling.  The last work-group to finish
+// returns the counters to zero, so one launch can be replayed (hipGraph) without a reset node.
+#include <hip/hip_ext.h>
+
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+
+#include "sg_internal.h"
+#include "tile_body.h"
+
+namespace sg {
+
+
+template <int BM, int BN>
+__global__ __launch_bounds__(256) void sg_gemm_grouped(const GroupProblem* __restrict__ probs, int G,
+                                                        int total_tiles, int out_bf16,
+                                                        int* __restrict__ counters) {
+    __shared__ __attribute__((aligned(16))) uint16_t smem[smem_elems<BM, BN>()];
+    __shared__ int s_tile;
+    for (;;) {
+        __syncthreads();                       // previous tile done with the LDS and s_tile
+        if (threadIdx.x == 0) s_tile = atomicAdd(&counters[0], 1);
+        __syncthreads();
+        const int t = s_tile;
+        if (t >= total_tiles) break;           // every work-group leaves once the queue is empty
+        int lo = 0, hi = G - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (probs[mid].tile_begin <= t) lo = mid;
+            else hi = mid - 1;
+        }
+        const GroupProblem& q = probs[lo];
+        const int local = t - q.tile_begin;
+        const int tm = local % q.tiles_m;      // M fastest: consecutive tiles share a B panel
+        const int tn = local / q.tiles_m;
+        KArgs a;
+        a.A = q.A; a.B = q.B; a.C = q.C; a.add = nullptr;
+        a.lda = q.lda; a.ldb = q.ldb; a.ldc = q.ldc; a.ldadd = 0; a.ws_slice = 0;
+        a.M = q.M; a.N = q.N; a.K = q.K; a.Kl = q.K; a.k_chunk = ((q.K + kBK - 1) / kBK) * kBK;
+        a.tiles_m = q.tiles_m; a.tiles_n = q.tiles_n;
+        a.out_bf16 = out_bf16; a.add_kind = ADD_NONE;
+        a.vec_ok = q.vec_ok;
+        a.a_bytes = q.a_bytes; a.b_bytes = q.b_bytes;
+        if (q.aligned) tile_body<BM, BN, true>(a, tm * BM, tn * BN, 0, smem);
+        else tile_body<BM, BN, false>(a, tm * BM, tn * BN, 0, smem);
+    }
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const int done = atomicAdd(&counters[1], 1);
+        if (done == (int)gridDim.x - 1) {      // last one out: reset for the next launch
+            atomicExch(&counters[0], 0);
+            atomicExch(&counters[1], 0);
+        }
+    }
+}
+
+typedef void (*GroupedKernel)(const GroupProblem*, int, int, int, int*);
+
+static GroupedKernel grouped_kernel(int tile) {
+    switch (tile) {
+        case 0: return sg_gemm_grouped<256, 256>;
+        case 1: return sg_gemm_grouped<256, 128>;
+        case 2: return sg_gemm_grouped<128, 256>;
+        case 3: return sg_gemm_grouped<128, 128>;
+        case 4: return sg_gemm_grouped<128, 64>;
+        case 5: return sg_gemm_grouped<64, 128>;
+        default: return sg_gemm_grouped<64, 64>;
+    }
+}
+
+int grouped_fill(const sg_problem* probs, int G, int tile, int c_dtype, bool lpt, GroupProblem* out,
+                 int* order, int* total_tiles, double* flops) {
+    const TileShape ts = kTiles[tile];
+    std::iota(order, order + G, 0);
+    if (lpt) std::stable_sort(order, order + G, [&](int a, int b) { return probs[a].K > probs[b].K; });
+    int64_t tiles = 0;
+    double fl = 0.0;
+    const size_t esz = c_dtype == SG_BF16 ? 2 : 4;
+    for (int i = 0; i < G; ++i) {
+        const sg_problem& q = probs[order[i]];
+        GroupProblem& g = out[i];
+        g.A = (const uint16_t*)q.A; g.B = (const uint16_t*)q.B; g.C = q.C;
+        g.lda = q.lda; g.ldb = q.ldb; g.ldc = q.ldc;
+        g.M = (int)q.M; g.N = (int)q.N; g.K = (int)q.K;
+        g.tiles_m = (int)((q.M + ts.bm - 1) / ts.bm);
+        g.tiles_n = (int)((q.N + ts.bn - 1) / ts.bn);
+        g.tile_begin = (int)tiles;
+        const int64_t ab = ((q.M - 1) * q.lda + q.K) * 2, bb = ((q.K - 1) * q.ldb + q.N) * 2;
+        const bool al = q.lda % 8 == 0 && q.ldb % 8 == 0 && q.K % 8 == 0 && q.N % 8 == 0 &&
+                        (uintptr_t)q.A % 16 == 0 && (uintptr_t)q.B % 16 == 0 && ab < 0x7FFFFFFF &&
+                        bb < 0x7FFFFFFF;
+        g.aligned = al ? 1 : 0;
+        g.a_bytes = al ? (int)ab : 0;
+        g.b_bytes = al ? (int)bb : 0;
+        g.vec_ok = (q.ldc % 4 == 0 && (uintptr_t)q.C % (4 * esz) == 0) ? 1 : 0;
+        tiles += (int64_t)g.tiles_m * g.tiles_n;
+        fl += 2.0 * (double)q.M * (double)q.N * (double)q.K;
+        if (tiles > 0x7FFFFFFF) return fail(SG_EINVAL, "grouped: too many tiles");
+    }
+    *total_tiles = (int)tiles;
+    *flops = fl;
+    return SG_OK;
+}
+
+int grouped_grid(int tile, int device, int total_tiles, int grid_wgs, int* grid) {
+    int per_cu = 1, cus = 0;
+    SG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, grouped_kernel(tile), 256, 0));
+    SG_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device));
+    int g = std::max(1, per_cu) * cus;
+    if (grid_wgs > 0) g = grid_wgs;
+    *grid = std::min(g, std::max(1, total_tiles));
+    return SG_OK;
+}
+
+int grouped_enqueue(int tile, const GroupProblem* d_probs, int G, int total_tiles, int grid,
+                    int c_dtype, int* d_counters, hipStream_t s, hipEvent_t start, hipEvent_t stop) {
+    hipExtLaunchKernelGGL(grouped_kernel(tile), dim3(grid), dim3(256), 0, s, start, stop, 0, d_probs, G,
+                          total_tiles, c_dtype == SG_BF16 ? 1 : 0, d_counters);
+    SG_HIP(hipGetLastError());
+    return SG_OK;
+}
+
+}  // namespace sg
+
+using namespace sg;
+
+struct sg_group_plan {
+    int device = 0;
+    int G = 0;
+    int c_dtype = SG_BF16;
+    sg_group_cfg cfg{};
+    int total_tiles = 0;
+    int grid = 0;
+    double flops = 0.0;
+    std::vector<sg_problem> probs;    // host copy, in queue order
+    GroupProblem* d_probs = nullptr;
+    int* d_counters = nullptr;
+};
+
+struct sg_graph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+int validate_problems(int G, const sg_problem* p) {
+    if (G <= 0 || !p) return fail(SG_EINVAL, "grouped: empty problem list");
+    for (int i = 0; i < G; ++i) {
+        const sg_problem& q = p[i];
+        if (q.M <= 0 || q.N <= 0 || q.K <= 0) return fail(SG_EINVAL, "grouped: every problem needs M, N, K > 0");
+        if (!q.A || !q.B || !q.C) return fail(SG_EINVAL, "grouped: NULL operand");
+        if (q.lda < q.K || q.ldb < q.N || q.ldc < q.N) return fail(SG_EINVAL, "grouped: leading dimension too small");
+        if (q.M > 0x7FFFFFFF || q.N > 0x7FFFFFFF || q.K > 0x7FFFFFFF) return fail(SG_EINVAL, "grouped: dimension too large");
+    }
+    return SG_OK;
+}
+
+// Build descriptors for the tile shape, in longest-tile-first order, and upload them.
+int plan_upload(sg_group_plan* pl, const sg_problem* probs, hipStream_t s) {
+    const int G = pl->G;
+    std::vector<GroupProblem> h(G);
+    std::vector<int> order(G);
+    int rc = grouped_fill(probs, G, pl->cfg.tile, pl->c_dtype, pl->cfg.order == 0, h.data(),
+                          order.data(), &pl->total_tiles, &pl->flops);
+    if (rc) return rc;
+    pl->probs.resize(G);
+    for (int i = 0; i < G; ++i) pl->probs[i] = probs[order[i]];
+    if (!pl->d_probs) SG_HIP(hipMalloc(&pl->d_probs, sizeof(GroupProblem) * G));
+    SG_HIP(hipMemcpyAsync(pl->d_probs, h.data(), sizeof(GroupProblem) * G, hipMemcpyHostToDevice, s));
+    SG_HIP(hipStreamSynchronize(s));
+    return grouped_grid(pl->cfg.tile, pl->device, pl->total_tiles, pl->cfg.grid_wgs, &pl->grid);
+}
+
+int plan_enqueue(sg_group_plan* pl, hipStream_t s, hipEvent_t start = nullptr, hipEvent_t stop = nullptr) {
+    return grouped_enqueue(pl->cfg.tile, pl->d_probs, pl->G, pl->total_tiles, pl->grid, pl->c_dtype,
+                           pl->d_counters, s, start, stop);
+}
+
+}  // namespace
+
+extern "C" {
+
+int sg_group_plan_create(sg_ctx* ctx, int G, const sg_problem* probs, int c_dtype,
+                         const sg_group_cfg* cfg, void* stream, sg_group_plan** out) {
+    if (!ctx || !out) return fail(SG_EINVAL, "NULL argument");
+    *out = nullptr;
+    int rc = validate_problems(G, probs);
+    if (rc) return rc;
+    if (c_dtype != SG_F32 && c_dtype != SG_BF16) return fail(SG_EINVAL, "bad c_dtype");
+    if (cfg && (cfg->tile < 0 || cfg->tile >= kNumTiles || (cfg->order != 0 && cfg->order != 1) || cfg->grid_wgs < 0))
+        return fail(SG_EINVAL, "bad group configuration");
+    int dev = 0;
+    SG_HIP(hipGetDevice(&dev));
+    hipStream_t s = (hipStream_t)stream;
+    sg_group_plan* pl = new (std::nothrow) sg_group_plan();
+    if (!pl) return fail(SG_ENOMEM, "plan allocation failed");
+    pl->device = dev;
+    pl->G = G;
+    pl->c_dtype = c_dtype;
+    if (hipMalloc(&pl->d_counters, 2 * sizeof(int)) != hipSuccess) {
+        delete pl;
+        return fail(SG_ENOMEM, "grouped: counter allocation failed");
+    }
+    // counters start at zero once; every launch returns them to zero itself
+    if (hipMemset(pl->d_counters, 0, 2 * sizeof(int)) != hipSuccess) {
+        sg_group_plan_destroy(pl);
+        return fail(SG_EHIP, "grouped: counter reset failed");
+    }
+    if (cfg) {
+        pl->cfg = *cfg;
+        rc = plan_upload(pl, probs, s);
+    } else {
+        // autotune: every tile shape of the family, longest-K-first queue, best of 3 timed runs
+        hipEvent_t e0, e1;
+        SG_HIP(hipEventCreate(&e0));
+        SG_HIP(hipEventCreate(&e1));
+        double best = INFINITY;
+        sg_group_cfg best_cfg{3, 0, 0};
+        for (int t = 0; t < kNumTiles && rc == SG_OK; ++t) {
+            pl->cfg = sg_group_cfg{t, 0, 0};
+            rc = plan_upload(pl, probs, s);
+            if (rc) break;
+            rc = plan_enqueue(pl, s);                         // warm-up
+            double tmin = INFINITY;
+            for (int r = 0; r < 3 && rc == SG_OK; ++r) {
+                rc = plan_enqueue(pl, s, e0, e1);
+                if (rc) break;
+                if (hipEventSynchronize(e1) != hipSuccess) { rc = fail(SG_EHIP, "grouped: timing failed"); break; }
+                float ms = 0.f;
+                (void)hipEventElapsedTime(&ms, e0, e1);
+                tmin = std::min(tmin, (double)ms);
+            }
+            if (rc == SG_OK && tmin < best) {
+                best = tmin;
+                best_cfg = pl->cfg;
+            }
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        if (rc == SG_OK) {
+            pl->cfg = best_cfg;
+            rc = plan_upload(pl, probs, s);
+        }
+    }
+    if (rc) {
+        sg_group_plan_destroy(pl);
+        return rc;
+    }
+    *out = pl;
+    return SG_OK;
+}
+
+int sg_group_plan_launch(sg_group_plan* pl, void* stream) {
+    if (!pl) return fail(SG_EINVAL, "NULL plan");
+    return plan_enqueue(pl, (hipStream_t)stream);
+}
+
+int sg_group_plan_update(sg_group_plan* pl, const sg_problem* probs, void* stream) {
+    if (!pl) return fail(SG_EINVAL, "NULL plan");
+    int rc = validate_problems(pl->G, probs);
+    if (rc) return rc;
+    const int old_tiles = pl->total_tiles, old_grid = pl->grid;
+    rc = plan_upload(pl, probs, (hipStream_t)stream);
+    if (rc) return rc;
+    if (pl->total_tiles != old_tiles || pl->grid != old_grid) {
+        // a captured graph bakes in the launch arguments: signal that it must be recaptured
+        return fail(SG_EAGAIN, "grouped: tile count changed; recapture graphs that hold this plan");
+    }
+    return SG_OK;
+}
+
+int sg_group_plan_info(const sg_group_plan* pl, sg_group_cfg* cfg, int* total_tiles, int* grid, double* flops) {
+    if (!pl) return fail(SG_EINVAL, "NULL plan");
+    if (cfg) *cfg = pl->cfg;
+    if (total_tiles) *total_tiles = pl->total_tiles;
+    if (grid) *grid = pl->grid;
+    if (flops) *flops = pl->flops;
+    return SG_OK;
+}
+
+int sg_group_plan_destroy(sg_group_plan* pl) {
+    if (!pl) return SG_OK;
+    (void)hipDeviceSynchronize();
+    if (pl->d_probs) (void)hipFree(pl->d_probs);
+    if (pl->d_counters) (void)hipFree(pl->d_counters);
+    delete pl;
+    return SG_OK;
+}
+
+int sg_gemm_grouped(sg_ctx* ctx, int G, const sg_problem* probs, int c_dtype, const sg_group_cfg* cfg,
+                    void* stream) {
+    sg_group_plan* pl = nullptr;
+    sg_group_cfg def{3, 0, 0};
+    int rc = sg_group_plan_create(ctx, G, probs, c_dtype, cfg ? cfg : &def, stream, &pl);
+    if (rc) return rc;
+    rc = plan_enqueue(pl, (hipStream_t)stream);
+    if (rc == SG_OK && hipStreamSynchronize((hipStream_t)stream) != hipSuccess) rc = fail(SG_EHIP, "grouped: sync failed");
+    sg_group_plan_destroy(pl);
+    return rc;
+}
+
+int sg_graph_capture_groups(sg_group_plan* const* plans, int n, void* stream, sg_graph** out) {
+    if (!plans || n <= 0 || !out) return fail(SG_EINVAL, "bad arguments");
+    *out = nullptr;
+    hipStream_t s = (hipStream_t)stream;
+    if (!s) return fail(SG_EINVAL, "graph capture needs a non-null stream");
+    sg_graph* g = new (std::nothrow) sg_graph();
+    if (!g) return fail(SG_ENOMEM, "graph allocation failed");
+    SG_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    int rc = SG_OK;
+    for (int i = 0; i < n && rc == SG_OK; ++i) {
+        if (!plans[i]) { rc = fail(SG_EINVAL, "NULL plan"); break; }
+        rc = plan_enqueue(plans[i], s);
+    }
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(s, &graph);
+    if (rc == SG_OK && e != hipSuccess) rc = hip_fail(e, "hipStreamEndCapture");
+    if (rc == SG_OK) {
+        e = hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) rc = hip_fail(e, "hipGraphInstantiate");
+    }
+    g->graph = graph;
+    if (rc) {
+        sg_graph_destroy(g);
+        return rc;
+    }
+    *out = g;
+    return SG_OK;
+}
+
+int sg_graph_launch(sg_graph* g, void* stream) {
+    if (!g || !g->exec) return fail(SG_EINVAL, "NULL graph");
+    SG_HIP(hipGraphLaunch(g->exec, (hipStream_t)stream));
+    return SG_OK;
+}
+
+int sg_graph_destroy(sg_graph* g) {
+    if (!g) return SG_OK;
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    delete g;
+    return SG_OK;
+}
+
+}  // extern "C"

@@ -182,8 +182,11 @@ size_t plan_workspace(const Problem& pr, const std::vector<Leaf>& leaves, size_t
 
 // Enqueue one leaf.  Output routing (C FP32: accumulate in place; C BF16 with a K split:
 // accumulate in the FP32 plan accumulator W and round once in the last piece).
-int run_leaf(const Problem& pr, const Leaf& L, void* ws, size_t acc_bytes, hipStream_t s) {
+int run_leaf(const Problem& pr, const Leaf& L, void* ws, size_t acc_bytes, hipStream_t s,
+             hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr) {
     LaunchDesc d{};
+    d.ev_start = ev_start;
+    d.ev_stop = ev_stop;
     d.M = L.m; d.N = L.n; d.K = L.k; d.Ml = L.Ml; d.Nl = L.Nl; d.Kl = L.Kl;
     d.A = pr.A + L.m0 * pr.lda + L.k0; d.lda = pr.lda;
     d.B = pr.B + L.k0 * pr.ldb + L.n0; d.ldb = pr.ldb;
@@ -442,8 +445,10 @@ static int ensure_events(sg_ctx* ctx, size_t n) {
     return SG_OK;
 }
 
-// Time `reps` runs of the plan `leaves` (after one untimed run); every kernel launch is
-// bracketed by events.  Returns mean seconds per run; adds per-variant launch time to acct.
+// Time `reps` runs of the plan `leaves` (after one untimed run).  Every kernel launch carries
+// start/stop events stamped by its own dispatch packet, so a run's time is the sum of its
+// kernels' execution times (host launch gaps excluded).  Returns mean seconds per run; adds
+// per-variant kernel time, launch counts and algorithmic FLOP to the context's accounting.
 int time_plan(sg_ctx* ctx, const Problem& pr, const std::vector<Leaf>& leaves, int reps,
               hipStream_t s, double* sec, bool account) {
     size_t acc_bytes = 0;
@@ -454,33 +459,32 @@ int time_plan(sg_ctx* ctx, const Problem& pr, const std::vector<Leaf>& leaves, i
         if (rc) return rc;
     }
     const size_t nl = leaves.size();
-    const size_t ne = (size_t)reps * nl + 1;
+    const size_t ne = 2 * (size_t)reps * nl;
     rc = ensure_events(ctx, ne);
     if (rc) return rc;
     size_t e = 0;
     for (int r = 0; r < reps; ++r)
         for (const Leaf& L : leaves) {
-            SG_HIP(hipEventRecord(ctx->events[e++], s));
-            rc = run_leaf(pr, L, ctx->ws, acc_bytes, s);
+            rc = run_leaf(pr, L, ctx->ws, acc_bytes, s, ctx->events[e], ctx->events[e + 1]);
             if (rc) return rc;
+            e += 2;
         }
-    SG_HIP(hipEventRecord(ctx->events[e], s));
-    SG_HIP(hipEventSynchronize(ctx->events[e]));
-    float total_ms = 0.f;
-    SG_HIP(hipEventElapsedTime(&total_ms, ctx->events[0], ctx->events[e]));
-    *sec = (double)total_ms * 1e-3 / reps;
-    if (account) {
-        e = 0;
-        for (int r = 0; r < reps; ++r)
-            for (const Leaf& L : leaves) {
-                float ms = 0.f;
-                SG_HIP(hipEventElapsedTime(&ms, ctx->events[e], ctx->events[e + 1]));
-                ++e;
+    SG_HIP(hipEventSynchronize(ctx->events[ne - 1]));
+    double total = 0.0;
+    e = 0;
+    for (int r = 0; r < reps; ++r)
+        for (const Leaf& L : leaves) {
+            float ms = 0.f;
+            SG_HIP(hipEventElapsedTime(&ms, ctx->events[e], ctx->events[e + 1]));
+            e += 2;
+            total += (double)ms * 1e-3;
+            if (account) {
                 ctx->acct_launches[L.variant] += 1;
                 ctx->acct_seconds[L.variant] += (double)ms * 1e-3;
                 ctx->acct_flops[L.variant] += 2.0 * (double)L.m * (double)L.n * (double)L.k;
             }
-    }
+        }
+    *sec = total / reps;
     return SG_OK;
 }
 

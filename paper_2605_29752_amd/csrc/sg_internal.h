@@ -33,6 +33,9 @@ struct LaunchDesc {
     int out_bf16;                  // 1: C is BF16, 0: FP32
     const void* add; int64_t ldadd;
     int add_kind;                  // 0 none, 1 FP32 addend, 2 BF16 addend (may alias C)
+    // optional timing events stamped by the dispatch itself (start of the first kernel of the
+    // launch, end of its last kernel); nullptr = no timing
+    hipEvent_t ev_start = nullptr, ev_stop = nullptr;
 };
 
 enum { ADD_NONE = 0, ADD_F32 = 1, ADD_BF16 = 2 };
@@ -55,6 +58,32 @@ size_t launch_workspace_bytes(int variant, const LaunchDesc& d);
 // Enqueue one launch (and, for S > 1, its reduction).  ws must hold launch_workspace_bytes.
 int launch_variant(int variant, const LaunchDesc& d, void* ws, hipStream_t stream);
 int lds_bytes_of_tile(int tile);
+
+// Device descriptor of one problem of a grouped launch.
+struct GroupProblem {
+    const uint16_t* A;
+    const uint16_t* B;
+    void* C;
+    int64_t lda, ldb, ldc;
+    int M, N, K;
+    int tile_begin;      // first queue index of this problem's tiles
+    int tiles_m, tiles_n;
+    int aligned;
+    int vec_ok;          // C rows allow 4-wide vector stores
+    int a_bytes, b_bytes;
+};
+
+// Grouped launch building blocks (also used by the server, which stages descriptors itself).
+// Fill host descriptors for tile shape `tile`; order[i] receives the caller's index of queue
+// entry i (longest K first when lpt, else as given).
+int grouped_fill(const sg_problem* probs, int G, int tile, int c_dtype, bool lpt, GroupProblem* out,
+                 int* order, int* total_tiles, double* flops);
+// Resident work-groups for the tile shape on `device` (capped at the tile count).
+int grouped_grid(int tile, int device, int total_tiles, int grid_wgs, int* grid);
+// Enqueue one persistent launch over device descriptors; counters: 2 ints, zero before the
+// first launch, returned to zero by every launch.
+int grouped_enqueue(int tile, const GroupProblem* d_probs, int G, int total_tiles, int grid,
+                    int c_dtype, int* d_counters, hipStream_t s, hipEvent_t start, hipEvent_t stop);
 
 // Device generator launcher.
 int launch_fill(uint16_t* dst, int64_t n, uint64_t seed, uint64_t stream_id, int64_t offset,

@@ -1,0 +1,346 @@
+// Tile body of the BF16 NN GEMM family for gfx950: one BM x BN tile of C = A * B over a K range.
+// Shared by the per-call kernel (one tile per work-group) and the persistent grouped kernel
+// (many tiles of many problems per work-group).  The design notes are in gemm_tile.hip.
+#pragma once
+
+#include "sg_internal.h"
+
+namespace sg {
+
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2_t __attribute__((ext_vector_type(2)));
+
+
+struct KArgs {
+    const uint16_t* A;
+    const uint16_t* B;
+    void* C;
+    const void* add;
+    int64_t lda, ldb, ldc, ldadd;
+    int64_t ws_slice;   // elements between split-K partial slices
+    int M, N, K;        // data bounds
+    int Kl;             // K extent of the launch
+    int k_chunk;        // K elements per split (multiple of 64)
+    int tiles_m, tiles_n;
+    int out_bf16;
+    int add_kind;
+    int vec_ok;         // C / addend rows allow 4-wide vector access
+    int a_bytes, b_bytes;   // readable extents of A and B from their base (buffer range checks)
+};
+
+constexpr int LDK = kBK + 8;   // padded LDS row (elements)
+
+__device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
+    uint32_t u = __builtin_bit_cast(uint32_t, f);
+    if ((u & 0x7FFFFFFFu) > 0x7F800000u) return 0x7FC0;   // NaN stays NaN
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ float bf16_to_f32(uint16_t h) {
+    return __builtin_bit_cast(float, ((uint32_t)h) << 16);
+}
+
+// Tile index of this work-group.  Work-groups are handed to the 8 XCDs round robin; the
+// remap gives each XCD one contiguous run of tiles (so tiles sharing operand panels share an
+// L2), and the run is rastered in groups of 8 tile rows.
+__device__ __forceinline__ void tile_coords(int tiles_m, int tiles_n, int& tm, int& tn) {
+    const int nwg = tiles_m * tiles_n;
+    const int b = blockIdx.x;
+    const int x = b & 7, q = nwg >> 3, r = nwg & 7;
+    const int logical = x * q + (x < r ? x : r) + (b >> 3);
+    constexpr int GM = 8;
+    const int group = GM * tiles_n;
+    const int g = logical / group;
+    const int first_m = g * GM;
+    const int gm = min(tiles_m - first_m, GM);
+    const int local = logical - g * group;
+    tm = first_m + local % gm;
+    tn = local / gm;
+}
+
+// Operand staging of one K step in registers.  A: A_CHUNKS 16-byte chunks along K.  B: an
+// 8 (K) x NB (N) block, one row of NB elements per register group.
+template <int BM, int BN>
+struct Stage {
+    static constexpr int A_CHUNKS = BM * (kBK / 8) / 256;
+    static constexpr int NB = BN / 32;
+    u32x4_t a[A_CHUNKS];
+    uint32_t b[8][NB / 2];
+};
+
+template <int BM, int BN>
+constexpr int smem_elems() { return 2 * (BM + BN) * LDK; }
+
+// One BM x BN tile of C at (m0, n0) over the K range of split kz.  Called by all 256 threads of
+// a work-group; smem holds smem_elems<BM, BN>() elements.
+template <int BM, int BN, bool ALIGNED>
+__device__ __forceinline__ void tile_body(const KArgs& p, const int m0, const int n0, const int kz,
+                                          uint16_t* __restrict__ smem) {
+#ifndef SG_PREFETCH_DEPTH
+#define SG_PREFETCH_DEPTH 1
+#endif
+    // K steps of global loads in flight.  One: a second staging set costs enough registers to
+    // halve the resident work-groups of the 128 x 128 tile, which loses more than it hides.
+    constexpr int DEPTH = (BM * BN >= 256 * 128) ? 1 : SG_PREFETCH_DEPTH;
+    constexpr int WM = BM / 2, WN = BN / 2;        // per-wave tile
+    constexpr int FM = WM / 16, FN = WN / 16;      // MFMA fragments per wave
+    constexpr int A_CHUNKS = Stage<BM, BN>::A_CHUNKS;
+    constexpr int NB = Stage<BM, BN>::NB;          // B block width (columns) per thread
+    constexpr int STAGE = (BM + BN) * LDK;         // elements per LDS stage
+    static_assert(A_CHUNKS >= 1 && NB >= 2 && NB <= 8, "tile shape");
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int lr = lane & 15, lg = lane >> 4;
+
+    const int kb = kz * p.k_chunk;
+    const int ke = min(p.Kl, kb + p.k_chunk);
+    const int nk = (ke - kb + kBK - 1) / kBK;
+
+    // Per-thread load geometry.  c: the thread's 8-wide K chunk (same for A and B).
+    const int c = tid & 7;
+    const int nb = tid >> 3;                       // B column block
+    const int gn = n0 + nb * NB;
+
+    // Buffer resources: a read whose byte offset is at or past num_records returns zero, so
+    // out-of-range elements are predicated without branches by moving their offset out.
+    constexpr uint32_t kOut = 0x80000000u;
+    const __amdgpu_buffer_rsrc_t rA = __builtin_amdgcn_make_buffer_rsrc((void*)p.A, (short)0, p.a_bytes, 0x00020000);
+    const __amdgpu_buffer_rsrc_t rB = __builtin_amdgcn_make_buffer_rsrc((void*)p.B, (short)0, p.b_bytes, 0x00020000);
+    // One per-lane base offset per operand; chunk, row and step offsets are uniform (scalar)
+    // strides added on the fly, so no per-chunk offsets occupy registers across the loop.
+    const int rowb = tid >> 3;                     // A row of chunk 0 within the tile
+    const int mrem = p.M - m0;                     // valid A rows of this tile
+    const uint32_t baseA = (uint32_t)(((int64_t)(m0 + rowb) * p.lda + kb + c * 8) * 2);
+    const uint32_t baseB = (uint32_t)(((int64_t)(kb + c * 8) * p.ldb + gn) * 2);
+    const uint32_t rowStrideA = (uint32_t)(32 * p.lda * 2);   // 32 rows between A chunks
+    const uint32_t rowStrideB = (uint32_t)(p.ldb * 2);
+    const bool colB = gn < p.N;
+
+    auto load = [&](Stage<BM, BN>& s, int kt) {
+        const int k0 = kb + kt * kBK;
+        if constexpr (ALIGNED) {
+            const bool kA = k0 + c * 8 < p.K;      // K % 8 == 0: a chunk is wholly in or out
+            const uint32_t stepA = (uint32_t)(kt * kBK * 2);
+#pragma unroll
+            for (int i = 0; i < A_CHUNKS; ++i) {
+                const bool ok = kA && (rowb + 32 * i < mrem);
+                uint32_t o = ok ? baseA + (uint32_t)i * rowStrideA + stepA : kOut;
+                asm volatile("" : "+v"(o));        // keep the select: no load duplicated per branch
+                s.a[i] = __builtin_bit_cast(u32x4_t, __builtin_amdgcn_raw_buffer_load_b128(rA, (int)o, 0, 0));
+            }
+            const uint32_t stepB = (uint32_t)(kt * kBK) * rowStrideB;
+#pragma unroll
+            for (int r = 0; r < 8; ++r) {
+                const bool ok = colB && (k0 + c * 8 + r < p.K);
+                uint32_t o = ok ? baseB + stepB + (uint32_t)r * rowStrideB : kOut;
+                asm volatile("" : "+v"(o));
+                if constexpr (NB == 8) {
+                    u32x4_t v = __builtin_bit_cast(u32x4_t, __builtin_amdgcn_raw_buffer_load_b128(rB, (int)o, 0, 0));
+                    s.b[r][0] = v[0]; s.b[r][1] = v[1]; s.b[r][2] = v[2]; s.b[r][3] = v[3];
+                } else if constexpr (NB == 4) {
+                    u32x2_t v = __builtin_bit_cast(u32x2_t, __builtin_amdgcn_raw_buffer_load_b64(rB, (int)o, 0, 0));
+                    s.b[r][0] = v[0]; s.b[r][1] = v[1];
+                } else {
+                    s.b[r][0] = __builtin_amdgcn_raw_buffer_load_b32(rB, (int)o, 0, 0);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < A_CHUNKS; ++i) {
+                const int gm = m0 + ((tid + i * 256) >> 3), gk = k0 + c * 8;
+                const uint16_t* rowp = p.A + (int64_t)gm * p.lda;
+                uint32_t w[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int k_lo = gk + 2 * e, k_hi = k_lo + 1;
+                    uint32_t lo = (gm < p.M && k_lo < p.K) ? rowp[k_lo] : 0u;
+                    uint32_t hi = (gm < p.M && k_hi < p.K) ? rowp[k_hi] : 0u;
+                    w[e] = lo | (hi << 16);
+                }
+                s.a[i] = u32x4_t{w[0], w[1], w[2], w[3]};
+            }
+#pragma unroll
+            for (int r = 0; r < 8; ++r) {
+                const int gk = k0 + c * 8 + r;
+                const uint16_t* src = p.B + (int64_t)gk * p.ldb + gn;
+#pragma unroll
+                for (int w = 0; w < NB / 2; ++w) {
+                    const int n_lo = gn + 2 * w, n_hi = n_lo + 1;
+                    uint32_t lo = (gk < p.K && n_lo < p.N) ? src[2 * w] : 0u;
+                    uint32_t hi = (gk < p.K && n_hi < p.N) ? src[2 * w + 1] : 0u;
+                    s.b[r][w] = lo | (hi << 16);
+                }
+            }
+        }
+    };
+
+    // registers -> LDS: A as is; B transposed in registers to K-contiguous rows.
+    auto store = [&](const Stage<BM, BN>& s, int buf) {
+        uint16_t* As = smem + buf * STAGE;
+        uint16_t* Bs = As + BM * LDK;
+#pragma unroll
+        for (int i = 0; i < A_CHUNKS; ++i) {
+            const int row = (tid + i * 256) >> 3;
+            *(u32x4_t*)(As + row * LDK + c * 8) = s.a[i];
+        }
+#pragma unroll
+        for (int e = 0; e < NB; ++e) {
+            const int w = e >> 1, sh = (e & 1) * 16;
+            u32x4_t o;
+#pragma unroll
+            for (int pr = 0; pr < 4; ++pr) {
+                const uint32_t lo = (s.b[2 * pr][w] >> sh) & 0xFFFFu;
+                const uint32_t hi = (s.b[2 * pr + 1][w] >> sh) & 0xFFFFu;
+                o[pr] = lo | (hi << 16);
+            }
+            *(u32x4_t*)(Bs + (nb * NB + e) * LDK + c * 8) = o;
+        }
+    };
+
+    f32x4_t acc[FM][FN];
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) acc[i][j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+
+    auto compute = [&](int buf) {
+        const uint16_t* As = smem + buf * STAGE;
+        const uint16_t* Bs = As + BM * LDK;
+#pragma unroll
+        for (int ks = 0; ks < kBK / 32; ++ks) {
+            // all fragments of this 32-deep slice are read first, so their LDS latency overlaps
+            bf16x8_t af[FM], bfr[FN];
+#pragma unroll
+            for (int i = 0; i < FM; ++i)
+                af[i] = *(const bf16x8_t*)(As + (wm * WM + i * 16 + lr) * LDK + ks * 32 + lg * 8);
+#pragma unroll
+            for (int j = 0; j < FN; ++j)
+                bfr[j] = *(const bf16x8_t*)(Bs + (wn * WN + j * 16 + lr) * LDK + ks * 32 + lg * 8);
+#pragma unroll
+            for (int i = 0; i < FM; ++i)
+#pragma unroll
+                for (int j = 0; j < FN; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bfr[j], af[i], acc[i][j], 0, 0, 0);
+            // the largest tile would otherwise keep both slices' fragments live and spill
+            // issue order: every fragment read of the slice, then its MFMAs
+            __builtin_amdgcn_sched_group_barrier(0x100, FM + FN, 0);
+            __builtin_amdgcn_sched_group_barrier(0x008, FM * FN, 0);
+            if constexpr (FM * FN >= 64) __builtin_amdgcn_sched_barrier(0);
+        }
+    };
+
+    // Pipeline: the global loads of step kt+2 are in flight while step kt is multiplied and
+    // step kt+1 (loaded one step earlier) is written to the other LDS stage.
+    // Large tiles (DEPTH 1) hold one staging set: their MFMA work per step already covers the
+    // load latency, and a second set would not fit the register file.
+    if constexpr (DEPTH == 2) {
+        Stage<BM, BN> s0, s1;
+        if (nk > 0) load(s0, 0);
+        if (nk > 1) load(s1, 1);
+        if (nk > 0) store(s0, 0);
+        __syncthreads();
+        for (int kt = 0; kt < nk; kt += 2) {
+            if (kt + 2 < nk) load(s0, kt + 2);
+            compute(0);
+            if (kt + 1 < nk) store(s1, 1);
+            __syncthreads();
+            if (kt + 1 >= nk) break;
+            if (kt + 3 < nk) load(s1, kt + 3);
+            compute(1);
+            if (kt + 2 < nk) store(s0, 0);
+            __syncthreads();
+        }
+    } else {
+        Stage<BM, BN> s0;
+        if (nk > 0) {
+            load(s0, 0);
+            store(s0, 0);
+        }
+        __syncthreads();
+        for (int kt = 0; kt < nk; ++kt) {
+            if (kt + 1 < nk) load(s0, kt + 1);
+            compute(kt & 1);
+            if (kt + 1 < nk) store(s0, (kt + 1) & 1);
+            __syncthreads();
+        }
+    }
+
+    // ---- epilogue ------------------------------------------------------------------------------
+    // Each wave stages one 16-row band of its C sub-tile at a time in its own LDS slice (the
+    // main loop ended with a barrier, so the operand stages are free), then writes the band out
+    // row by row: lanes cover 4 consecutive columns each, so a wave stores whole row segments.
+    constexpr int EPAD = WN + 4;                          // f32 row of the band, padded
+    static_assert(4 * 16 * EPAD * 4 <= 2 * STAGE * 2, "epilogue staging must fit the LDS");
+    float* band = (float*)smem + wave * 16 * EPAD;
+    const int64_t zoff = (int64_t)kz * p.ws_slice;
+    constexpr int COLS4 = WN / 4;                         // 4-column groups per band row
+    constexpr int ROWS_PER_PASS = 64 / COLS4;             // band rows written per pass
+#pragma unroll
+    for (int i = 0; i < FM; ++i) {
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+            *(f32x4_t*)(band + lr * EPAD + j * 16 + lg * 4) = acc[i][j];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const int mb = m0 + wm * WM + i * 16;
+        const int nbase = n0 + wn * WN + (lane % COLS4) * 4;
+#pragma unroll 1
+        for (int r = lane / COLS4; r < 16; r += ROWS_PER_PASS) {
+            const int m = mb + r;
+            const int n = nbase;
+            if (m >= p.M || n >= p.N) continue;
+            f32x4_t v = *(const f32x4_t*)(band + r * EPAD + (lane % COLS4) * 4);
+            const bool full = p.vec_ok && (n + 3 < p.N);
+            if (p.add_kind == ADD_F32) {
+                const float* ap = (const float*)p.add + (int64_t)m * p.ldadd + n;
+                if (full) {
+                    v += *(const f32x4_t*)ap;
+                } else {
+                    for (int e = 0; e < 4; ++e)
+                        if (n + e < p.N) v[e] += ap[e];
+                }
+            } else if (p.add_kind == ADD_BF16) {
+                const uint16_t* ap = (const uint16_t*)p.add + (int64_t)m * p.ldadd + n;
+                if (full) {
+                    const u32x2_t a2 = *(const u32x2_t*)ap;
+                    v[0] += bf16_to_f32(a2[0] & 0xFFFFu); v[1] += bf16_to_f32(a2[0] >> 16);
+                    v[2] += bf16_to_f32(a2[1] & 0xFFFFu); v[3] += bf16_to_f32(a2[1] >> 16);
+                } else {
+                    for (int e = 0; e < 4; ++e)
+                        if (n + e < p.N) v[e] += bf16_to_f32(ap[e]);
+                }
+            }
+            if (p.out_bf16) {
+                uint16_t* cp = (uint16_t*)p.C + zoff + (int64_t)m * p.ldc + n;
+                if (full) {
+                    u32x2_t o;
+                    o[0] = (uint32_t)f32_to_bf16_rne(v[0]) | ((uint32_t)f32_to_bf16_rne(v[1]) << 16);
+                    o[1] = (uint32_t)f32_to_bf16_rne(v[2]) | ((uint32_t)f32_to_bf16_rne(v[3]) << 16);
+                    *(u32x2_t*)cp = o;
+                } else {
+                    for (int e = 0; e < 4; ++e)
+                        if (n + e < p.N) cp[e] = f32_to_bf16_rne(v[e]);
+                }
+            } else {
+                float* cp = (float*)p.C + zoff + (int64_t)m * p.ldc + n;
+                if (full) {
+                    *(f32x4_t*)cp = v;
+                } else {
+                    for (int e = 0; e < 4; ++e)
+                        if (n + e < p.N) cp[e] = v[e];
+                }
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+}
+
+}  // namespace sg

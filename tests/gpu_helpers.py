@@ -59,3 +59,15 @@ def check_exact(out, A_bits, B_bits, c_dtype):
         want = synth.bf16_bits_to_f32(oracle.f64_to_bf16_rne(Cref)).astype(np.float64)
         bad = np.argwhere(out != want)
     assert bad.size == 0, "first mismatch at %s of %d" % (bad[0], len(bad))
+
+
+def device_bytes(ptr: int, nbytes: int) -> np.ndarray:
+    """Copy nbytes at a raw device address to the host (HIP runtime already loaded by torch)."""
+    import ctypes
+    import torch  # noqa: F401  (makes torch's HIP runtime the loaded one)
+    hip = ctypes.CDLL("libamdhip64.so.7")
+    out = np.empty(nbytes, dtype=np.uint8)
+    rc = hip.hipMemcpy(out.ctypes.data_as(ctypes.c_void_p), ctypes.c_void_p(ptr),
+                       ctypes.c_size_t(nbytes), 2)   # hipMemcpyDeviceToHost
+    assert rc == 0, rc
+    return out
