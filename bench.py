@@ -30,7 +30,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_BF16_TFLOPS = 2516.6       # MI355X dense BF16 MFMA (256 CUs x 4096 FLOP/clk x 2.4 GHz)
-DEFAULT_VARIANTS = "0,4,8,12,13,14,16,17,18,24,26,27"
+DEFAULT_VARIANTS = "0,4,8,12,13,14,16,17,18,19,24,26,27"
 
 
 def log(*a):
@@ -52,6 +52,26 @@ def stack_stats(sg, sec, sizes):
             "slice_k%d_mean" % int(sizes[-1]): float(sl.mean()),
             "slice_k%d_roughness_n" % int(sizes[-1]): slice_rough,
             "frac_of_peak_mean": st["mean"] / PEAK_BF16_TFLOPS}
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha1()
+    for f in ("tile_body.h", "gemm_tile.hip"):
+        h.update(open(os.path.join(ROOT, "paper_2605_29752_amd", "csrc", f), "rb").read())
+    return h.hexdigest()
+
+
+def traffic_bytes(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed counter summary, if it was taken on
+    the current kernel source (else None)."""
+    path = os.path.join(ROOT, "profiles", "traffic_landscape_sweep.json")
+    if not os.path.exists(path):
+        return None
+    t = json.load(open(path))
+    if t.get("kernel") != kernel or t.get("source_sha1") != kernel_source_hash():
+        return None
+    return t["hbm_bytes_per_launch"]
 
 
 def cpu_baseline(seconds_budget: float, seed: int):
@@ -87,6 +107,99 @@ def cpu_baseline(seconds_budget: float, seed: int):
             "aggregate_tflops": float(np.sum(flops) / np.sum(secs) / 1e12)}
 
 
+def run_grouped(args, sg, torch, ctx, stream):
+    """Config 4: 512 groups x 64 GEMMs, log-uniform dims in [64, 4096] rounded to multiples of 8;
+    one autotuned persistent grouped launch per group, all 512 captured in one hipGraph, versus
+    the same problems as 64 separate per-call launches per group."""
+    rng = np.random.default_rng(4)
+    G, NG = 64, args.groups
+
+    def dim():
+        return int(np.clip(8 * np.round(np.exp(rng.uniform(np.log(64), np.log(4096))) / 8), 64, 4096))
+
+    pool = 1 << 26
+    A = torch.empty(pool, dtype=torch.bfloat16, device="cuda")
+    B = torch.empty(pool, dtype=torch.bfloat16, device="cuda")
+    sg.fill_bf16(A, 4, 0)
+    sg.fill_bf16(B, 4, 1)
+    Cs = [torch.empty(4096 * 4096, dtype=torch.bfloat16, device="cuda") for _ in range(G)]
+    groups, flops = [], 0.0
+    for g in range(NG):
+        probs = []
+        for j in range(G):
+            M, N, K = dim(), dim(), dim()
+            oa = int(rng.integers(0, (pool - M * K) // 8 + 1)) * 8
+            ob = int(rng.integers(0, (pool - K * N) // 8 + 1)) * 8
+            probs.append((M, N, K, A.data_ptr() + 2 * oa, K, B.data_ptr() + 2 * ob, N, Cs[j].data_ptr(), N))
+            flops += 2.0 * M * N * K
+        groups.append(probs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plans = [sg.GroupPlan(ctx, pr, sg.BF16, stream=stream) for pr in groups]
+    tune_s = time.perf_counter() - t0
+    tiles = [p.info()["tile"] for p in plans]
+    log("grouped: autotuned %d groups in %.1f s; tiles %s" % (NG, tune_s, np.bincount(tiles, minlength=7).tolist()))
+    graph = sg.Graph(plans, stream)
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        best = []
+        for _ in range(reps):
+            e0.record(stream)
+            fn()
+            e1.record(stream)
+            e1.synchronize()
+            best.append(e0.elapsed_time(e1) * 1e-3)
+        return float(np.mean(best))
+
+    t_graph = timed(lambda: graph.launch(stream), args.steps)
+    t_plans = timed(lambda: [p.launch(stream) for p in plans], args.steps)
+    arrs = [sg._problems(pr) for pr in groups]
+    t_call_same = timed(lambda: [sg.gemm_batch(ctx, pr, sg.BF16, sg.MODE_VARIANT, 4 * t, stream, _arr=a)
+                                 for pr, t, a in zip(groups, tiles, arrs)], args.steps)
+    res = {"graph_tflops": flops / t_graph / 1e12, "grouped_no_graph_tflops": flops / t_plans / 1e12,
+           "percall_same_tile_tflops": flops / t_call_same / 1e12,
+           "graph_s": t_graph, "percall_same_tile_s": t_call_same, "flops": flops,
+           "groups": NG, "problems_per_group": G, "autotune_s": tune_s,
+           "tile_histogram": np.bincount(tiles, minlength=7).tolist()}
+    if ctx._table is not None:
+        t_call_best = timed(lambda: [sg.gemm_batch(ctx, pr, sg.BF16, sg.MODE_BEST, 0, stream, _arr=a)
+                                     for pr, a in zip(groups, arrs)], args.steps)
+        res["percall_best_of_n_tflops"] = flops / t_call_best / 1e12
+    res["speedup_vs_percall_same_tile"] = t_call_same / t_graph
+    graph.close()
+    for p in plans:
+        p.close()
+    return res
+
+
+def run_serve(args, sg, torch, ctx):
+    """Config 5: Poisson requests over four transformer-layer weights, grouped continuous
+    batching versus per-request dispatch, same tile shape, same arrivals."""
+    shapes = [(4096, 4096), (4096, 11008), (11008, 4096), (4096, 14336)]     # (K, N)
+    ws = []
+    for i, (K, N) in enumerate(shapes):
+        t = torch.empty(K * N, dtype=torch.bfloat16, device="cuda")
+        sg.fill_bf16(t, 5, 100 + i, kind=1, scale=0.02)
+        ws.append(t)
+    torch.cuda.synchronize()
+    out = {"rate_req_s": args.serve_rate, "duration_s": args.serve_seconds,
+           "warmup_s": args.serve_warmup, "tile": sg.variant_info(4 * args.serve_tile).name[:-3]}
+    for name, mode in (("grouped", sg.SERVE_GROUPED), ("per_request", sg.SERVE_PER_REQUEST)):
+        srv = sg.Server(ctx, [(K, N, t.data_ptr(), N) for (K, N), t in zip(shapes, ws)],
+                        hbm_budget=args.serve_budget_gb << 30, max_inflight=4, max_group=64,
+                        mode=mode, tile=args.serve_tile, max_m=8192, seed=5)
+        log("serving (%s) %.0f req/s for %.0f s" % (name, args.serve_rate, args.serve_seconds))
+        rep = srv.serve_poisson(args.serve_rate, args.serve_seconds, args.serve_warmup, 5, 8192)
+        srv.close()
+        out[name] = rep
+        log("  p50 %.2f ms p99 %.2f ms, %.1f req/s, %.1f TFLOP/s" % (rep["p50_ms"], rep["p99_ms"],
+                                                                   rep["req_per_s"], rep["tflops"]))
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -105,7 +218,23 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--dump", default=None, help="write per-shape arrays (.npz) here")
+    ap.add_argument("--workload", choices=["sweep", "grouped", "serve"], default="sweep",
+                    help="sweep: the landscape (headline) plus a serving leg; grouped: config 4; "
+                         "serve: config 5 at its full duration")
+    ap.add_argument("--groups", type=int, default=512)
+    ap.add_argument("--serve-rate", type=float, default=2000.0)
+    ap.add_argument("--serve-seconds", type=float, default=None,
+                    help="default 20 s inside the sweep workload, 60 s for --workload serve")
+    ap.add_argument("--serve-warmup", type=float, default=5.0)
+    ap.add_argument("--serve-tile", type=int, default=3)
+    ap.add_argument("--serve-budget-gb", type=int, default=64)
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving leg of the sweep")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="before the sweep, copy MIB MiB three times with a plain copy kernel (a "
+                         "known-size reference for hardware byte counters)")
     args = ap.parse_args()
+    if args.serve_seconds is None:
+        args.serve_seconds = 60.0 if args.workload == "serve" else 20.0
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -122,7 +251,36 @@ def main():
     props = torch.cuda.get_device_properties(dev)
     ctx = sg.Context(dev)
     ctx.set_plain_variant(args.plain_variant)
+    ctx.set_progress(2048)
     stream = torch.cuda.current_stream()
+    common = {"n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "scaling": "weak",
+              "vs_baseline": None, "dtype": "bf16", "data": "synthetic", "device": props.name}
+
+    if args.workload == "serve":
+        res = run_serve(args, sg, torch, ctx)
+        g, p = res["grouped"], res["per_request"]
+        print(json.dumps(dict(
+            metric="served p99 latency, continuous batching (Poisson %.0f req/s)" % args.serve_rate,
+            value=g["p99_ms"], unit="ms", higher_is_better=False,
+            ms_per_step=args.serve_seconds * 1e3,
+            config={"workload": "GEMM serving: Poisson %.0f req/s for %.0f s, M log-uniform 1..8192, "
+                                "(N,K) in {(4096,4096),(11008,4096),(4096,11008),(14336,4096)}, "
+                                "N(0,0.02) BF16, BF16 out, HBM budget %d GiB"
+                                % (args.serve_rate, args.serve_seconds, args.serve_budget_gb)},
+            serving=res, **common)), flush=True)
+        return
+    if args.workload == "grouped":
+        if args.table:
+            ctx.set_table(sg.Table.load(args.table))
+        res = run_grouped(args, sg, torch, ctx, stream)
+        print(json.dumps(dict(
+            metric="grouped BF16 GEMM throughput (hipGraph of persistent grouped launches)",
+            value=res["graph_tflops"], unit="TFLOP/s", higher_is_better=True,
+            ms_per_step=res["graph_s"] * 1e3,
+            config={"workload": "%d groups x 64 BF16 NN GEMMs, M,N,K log-uniform [64,4096] rounded "
+                                "to multiples of 8, BF16 out" % args.groups},
+            grouped=res, **common)), flush=True)
+        return
 
     n, step = args.n, args.step
     sizes = np.arange(1, n + 1, dtype=np.float64) * step
@@ -134,6 +292,14 @@ def main():
     sg.fill_bf16(A, args.seed, 0)           # same bits as the host generator (tested)
     sg.fill_bf16(B, args.seed, 1)
     torch.cuda.synchronize()
+
+    if args.calibrate_copy > 0:
+        src = torch.ones(args.calibrate_copy << 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     variants = [int(v) for v in args.variants.split(",")]
     if args.plain_variant not in variants:
@@ -204,7 +370,12 @@ def main():
     stacks["best_single_%s" % sg.variant_info(best_single).name] = \
         stack_stats(sg, T0all[variants.index(best_single)], sizes)
 
-    dom = int(np.argmax(ksec))
+    # dominant kernel: the unsplit variant with the most kernel time (a split variant's launch
+    # time also covers its reduction kernel, so it is not one kernel's duration)
+    unsplit = np.array([sg.variant_info(v).splits == 1 for v in range(sg.num_variants())])
+    dom = int(np.argmax(np.where(unsplit, ksec, -1.0)))
+    vi = sg.variant_info(dom)
+    dom_kernel = "sg_gemm_tile<%d, %d, true>" % (vi.bm, vi.bn)
     achieved = kflops[dom] / ksec[dom] / 1e12
     ex = stacks["dp_split_pad_executed"]
     plain = stacks["plain_%s" % sg.variant_info(args.plain_variant).name]
@@ -247,13 +418,19 @@ def main():
         "dp_actions": {names[a]: c / n ** 3 for a, c in sorted(actions.items())},
         "table_build_s": table_s,
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_BF16_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_BF16_TFLOPS, "traffic": None,
-                     "kernel": "sg_gemm_tile " + sg.variant_info(dom).name,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_BF16_TFLOPS,
+                     "traffic": traffic_bytes(dom_kernel),
+                     "kernel": dom_kernel, "variant": sg.variant_info(dom).name,
                      "launches": int(launches[dom]),
                      "avg_launch_us": ksec[dom] / max(launches[dom], 1) * 1e6,
                      "flop_per_launch": kflops[dom] / max(launches[dom], 1)},
         "device": props.name,
     }
+    if not args.no_serve:
+        srv = run_serve(args, sg, torch, ctx)
+        result["served_p50_ms"] = srv["grouped"]["p50_ms"]
+        result["served_p99_ms"] = srv["grouped"]["p99_ms"]
+        result["serving"] = srv
     if not args.no_cpu_baseline:
         log("cpu baseline")
         result["cpu_baseline"] = cpu_baseline(args.cpu_seconds, args.seed)

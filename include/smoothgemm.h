@@ -60,6 +60,9 @@ int sg_ctx_create(int device, sg_ctx** out);
 int sg_ctx_destroy(sg_ctx* ctx);
 /* Fixed variant used by SG_MODE_PLAIN (default: variant 0, the 256 x 256 tile, no split). */
 int sg_ctx_set_plain_variant(sg_ctx* ctx, int variant);
+/* every > 0: sweeps and table measurements print one progress line to stderr every `every`
+ * shapes; 0 (default) keeps them silent. */
+int sg_ctx_set_progress(sg_ctx* ctx, int every);
 /* Reserve at least `bytes` of workspace now, so later calls do not allocate. */
 int sg_ctx_reserve_workspace(sg_ctx* ctx, size_t bytes);
 
@@ -211,6 +214,12 @@ int sg_group_plan_destroy(sg_group_plan* plan);
 /* One-shot form: plan (cfg NULL = tile 128x128), launch, wait, free. */
 int sg_gemm_grouped(sg_ctx* ctx, int G, const sg_problem* probs, int c_dtype,
                     const sg_group_cfg* cfg, void* stream);
+
+/* Per-call form of the same work: every problem is one ordinary gemm_bf16_nn_ex call (beta 0,
+ * the given mode / variant), issued back to back on `stream` from the library — the baseline a
+ * grouped launch is compared with.  Stops at the first failing problem. */
+int sg_gemm_batch(sg_ctx* ctx, int G, const sg_problem* probs, int c_dtype, int mode, int variant,
+                  void* stream);
 
 /* hipGraph of n grouped launches in sequence (captured on `stream`, which must not be NULL).
  * Replays reuse the plans' device descriptors: update them with sg_group_plan_update. */

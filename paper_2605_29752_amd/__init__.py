@@ -68,6 +68,7 @@ _SIGS = {
     "sg_ctx_create": (_i32, [_i32, ctypes.POINTER(_p)]),
     "sg_ctx_destroy": (_i32, [_p]),
     "sg_ctx_set_plain_variant": (_i32, [_p, _i32]),
+    "sg_ctx_set_progress": (_i32, [_p, _i32]),
     "sg_ctx_reserve_workspace": (_i32, [_p, ctypes.c_size_t]),
     "sg_ctx_set_table": (_i32, [_p, _p]),
     "gemm_bf16_nn": (_i32, [_i64, _i64, _i64, _p, _p, _p]),
@@ -96,6 +97,7 @@ _SIGS = {
     "sg_group_plan_info": (_i32, [_p, _p, ctypes.POINTER(_i32), ctypes.POINTER(_i32), ctypes.POINTER(_d)]),
     "sg_group_plan_destroy": (_i32, [_p]),
     "sg_gemm_grouped": (_i32, [_p, _i32, _p, _i32, _p, _p]),
+    "sg_gemm_batch": (_i32, [_p, _i32, _p, _i32, _i32, _i32, _p]),
     "sg_graph_capture_groups": (_i32, [_p, _i32, _p, ctypes.POINTER(_p)]),
     "sg_graph_launch": (_i32, [_p, _p]),
     "sg_graph_destroy": (_i32, [_p]),
@@ -327,6 +329,9 @@ class Context:
     def set_plain_variant(self, v: int):
         check(lib().sg_ctx_set_plain_variant(self.handle, v))
 
+    def set_progress(self, every: int):
+        check(lib().sg_ctx_set_progress(self.handle, every))
+
     def reserve_workspace(self, nbytes: int):
         check(lib().sg_ctx_reserve_workspace(self.handle, nbytes))
 
@@ -508,6 +513,13 @@ class Server:
 
     def __del__(self):
         self.close()
+
+
+def gemm_batch(ctx: "Context", probs, c_dtype: int = BF16, mode: int = MODE_PLAIN, variant: int = 0,
+               stream=None, _arr=None):
+    """Per-call launches of every problem, issued back to back from the library."""
+    arr = _arr if _arr is not None else _problems(probs)
+    check(lib().sg_gemm_batch(ctx.handle, len(arr), arr, c_dtype, mode, variant, _stream_ptr(stream)))
 
 
 def gemm_grouped(ctx: "Context", probs, c_dtype: int = BF16, tile: int = 3, stream=None):

@@ -31,6 +31,7 @@ struct sg_ctx {
     int device = 0;
     int num_cus = 0;
     int plain_variant = 0;
+    int progress_every = 0;           // >0: a stderr line every this many shapes
     void* ws = nullptr;
     size_t ws_bytes = 0;
     const sg_table* table = nullptr;
@@ -326,6 +327,12 @@ int sg_ctx_set_plain_variant(sg_ctx* ctx, int variant) {
     return SG_OK;
 }
 
+int sg_ctx_set_progress(sg_ctx* ctx, int every) {
+    if (!ctx || every < 0) return fail(SG_EINVAL, "bad argument");
+    ctx->progress_every = every;
+    return SG_OK;
+}
+
 int sg_ctx_reserve_workspace(sg_ctx* ctx, size_t bytes) {
     if (!ctx) return fail(SG_EINVAL, "NULL ctx");
     DeviceGuard guard(ctx->device);
@@ -363,6 +370,22 @@ int gemm_bf16_nn_ex(sg_ctx* ctx, const sg_gemm_args* args, void* stream) {
     if (!ctx) return fail(SG_EINVAL, "NULL ctx");
     DeviceGuard guard(ctx->device);
     return gemm_impl(ctx, args, (hipStream_t)stream);
+}
+
+int sg_gemm_batch(sg_ctx* ctx, int G, const sg_problem* probs, int c_dtype, int mode, int variant,
+                  void* stream) {
+    if (!ctx || G < 0 || (G > 0 && !probs)) return fail(SG_EINVAL, "bad arguments");
+    DeviceGuard guard(ctx->device);
+    for (int i = 0; i < G; ++i) {
+        const sg_problem& q = probs[i];
+        sg_gemm_args a{};
+        a.M = q.M; a.N = q.N; a.K = q.K;
+        a.A = q.A; a.lda = q.lda; a.B = q.B; a.ldb = q.ldb; a.C = q.C; a.ldc = q.ldc;
+        a.c_dtype = c_dtype; a.beta = 0; a.mode = mode; a.variant = variant;
+        const int rc = gemm_impl(ctx, &a, (hipStream_t)stream);
+        if (rc) return rc;
+    }
+    return SG_OK;
 }
 
 int sg_num_variants(void) { return kNumVariants; }
@@ -522,6 +545,8 @@ extern "C" int sg_sweep(sg_ctx* ctx, const sg_shape* shapes, int64_t n, int mode
         }
         rc = time_plan(ctx, pr, leaves, reps, s, &out_sec[i], true);
         if (rc) return rc;
+        if (ctx->progress_every > 0 && (i + 1) % ctx->progress_every == 0)
+            std::fprintf(stderr, "[smoothgemm] sweep %lld / %lld shapes\n", (long long)(i + 1), (long long)n);
     }
     return SG_OK;
 }
@@ -566,6 +591,8 @@ int measure_t0(sg_ctx* ctx, const std::vector<sg_shape>& order, const std::vecto
             if (rc) return rc;
             T0[(size_t)v * ncells + cells[i]] = sec;
         }
+        if (ctx->progress_every > 0 && (i + 1) % ctx->progress_every == 0)
+            std::fprintf(stderr, "[smoothgemm] T0 %zu / %zu shapes x %d variants\n", i + 1, order.size(), nvar);
     }
     return SG_OK;
 }

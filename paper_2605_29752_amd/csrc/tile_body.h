@@ -79,12 +79,16 @@ constexpr int smem_elems() { return 2 * (BM + BN) * LDK; }
 template <int BM, int BN, bool ALIGNED>
 __device__ __forceinline__ void tile_body(const KArgs& p, const int m0, const int n0, const int kz,
                                           uint16_t* __restrict__ smem) {
-#ifndef SG_PREFETCH_DEPTH
-#define SG_PREFETCH_DEPTH 1
+#ifndef SG_DEPTH_LARGE
+#define SG_DEPTH_LARGE 1
 #endif
-    // K steps of global loads in flight.  One: a second staging set costs enough registers to
-    // halve the resident work-groups of the 128 x 128 tile, which loses more than it hides.
-    constexpr int DEPTH = (BM * BN >= 256 * 128) ? 1 : SG_PREFETCH_DEPTH;
+#ifndef SG_DEPTH_SMALL
+#define SG_DEPTH_SMALL 1
+#endif
+    // K steps of global loads in flight.  One for every tile: a second register staging set
+    // spills the tiles of 256 x 128 and up, and halves the resident work-groups of the smaller
+    // ones, which then no longer hide each other's latency.
+    constexpr int DEPTH = (BM * BN >= 256 * 128) ? SG_DEPTH_LARGE : SG_DEPTH_SMALL;
     constexpr int WM = BM / 2, WN = BN / 2;        // per-wave tile
     constexpr int FM = WM / 16, FN = WN / 16;      // MFMA fragments per wave
     constexpr int A_CHUNKS = Stage<BM, BN>::A_CHUNKS;
@@ -246,12 +250,16 @@ __device__ __forceinline__ void tile_body(const KArgs& p, const int m0, const in
         __syncthreads();
         for (int kt = 0; kt < nk; kt += 2) {
             if (kt + 2 < nk) load(s0, kt + 2);
+            __builtin_amdgcn_sched_barrier(0);     // keep the two halves' schedules apart
             compute(0);
+            __builtin_amdgcn_sched_barrier(0);
             if (kt + 1 < nk) store(s1, 1);
             __syncthreads();
             if (kt + 1 >= nk) break;
             if (kt + 3 < nk) load(s1, kt + 3);
+            __builtin_amdgcn_sched_barrier(0);
             compute(1);
+            __builtin_amdgcn_sched_barrier(0);
             if (kt + 2 < nk) store(s0, 0);
             __syncthreads();
         }
