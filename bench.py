@@ -57,7 +57,7 @@ def stack_stats(sg, sec, sizes):
 def kernel_source_hash() -> str:
     import hashlib
     h = hashlib.sha1()
-    for f in ("tile_body.h", "gemm_tile.hip"):
+    for f in ("tile_body.h", "tile_body_dma.h", "gemm_tile.hip"):
         h.update(open(os.path.join(ROOT, "paper_2605_29752_amd", "csrc", f), "rb").read())
     return h.hexdigest()
 
@@ -175,6 +175,46 @@ def run_grouped(args, sg, torch, ctx, stream):
     return res
 
 
+def run_offgrid(args, sg, torch, ctx, stream):
+    """Config 3: 4,096 GEMMs with M, N, K ~ U{1..8192} (seed 3), BF16 out.  The dispatch table is
+    measured on a step-512 grid {512..8192}^3 (4,096 cells; a step-128 grid to 8192 would be
+    262,144 cells), then the shapes run (a) naive pad-to-tile: the plain 256 x 256 kernel
+    predicated over the ragged edges, (b) best-of-N, (c) DP pad/split dispatch."""
+    step, n = 512, 16
+    pool = 8192 * 8192
+    A = torch.empty(pool, dtype=torch.bfloat16, device="cuda")
+    B = torch.empty(pool, dtype=torch.bfloat16, device="cuda")
+    C = torch.empty(pool, dtype=torch.bfloat16, device="cuda")
+    sg.fill_bf16(A, 3, 0)
+    sg.fill_bf16(B, 3, 1)
+    torch.cuda.synchronize()
+    variants = [int(v) for v in args.variants.split(",")]
+    t0 = time.perf_counter()
+    table = ctx.build_table(step, n, n, n, variants, A, B, C, c_dtype=sg.BF16,
+                            warmup=args.shape_warmup, reps=args.reps, order_seed=13, stream=stream)
+    table_s = time.perf_counter() - t0
+    ctx.set_table(table)
+    rng = np.random.default_rng(3)
+    shapes = [tuple(int(x) for x in s) for s in rng.integers(1, 8193, size=(4096, 3))]
+    fl = np.array([2.0 * m * nn * k for m, nn, k in shapes])
+    out = {"table_grid": "{%d..%d}^3 step %d" % (step, step * n, step), "table_build_s": table_s}
+    secs = {}
+    for name, mode in (("naive_pad_to_tile", sg.MODE_PLAIN), ("best_of_n", sg.MODE_BEST),
+                       ("dp_split_pad", sg.MODE_DP)):
+        log("off-grid: %s" % name)
+        sec = ctx.sweep(shapes, A, B, C, mode=mode, c_dtype=sg.BF16, warmup=args.shape_warmup,
+                        reps=args.reps, stream=stream)
+        secs[name] = sec
+        tf = fl / sec / 1e12
+        out[name] = {"mean_tflops": float(tf.mean()), "aggregate_tflops": float(fl.sum() / sec.sum() / 1e12),
+                     "total_s": float(sec.sum())}
+    r = secs["naive_pad_to_tile"] / secs["dp_split_pad"]
+    out["dp_vs_naive"] = {"mean_speedup": float(r.mean()), "median_speedup": float(np.median(r)),
+                          "frac_faster": float(np.mean(r > 1.0)), "frac_faster_10pct": float(np.mean(r > 1.1))}
+    ctx.set_table(None)
+    return out
+
+
 def run_serve(args, sg, torch, ctx):
     """Config 5: Poisson requests over four transformer-layer weights, grouped continuous
     batching versus per-request dispatch, same tile shape, same arrivals."""
@@ -218,7 +258,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--dump", default=None, help="write per-shape arrays (.npz) here")
-    ap.add_argument("--workload", choices=["sweep", "grouped", "serve"], default="sweep",
+    ap.add_argument("--workload", choices=["sweep", "grouped", "serve", "offgrid"], default="sweep",
                     help="sweep: the landscape (headline) plus a serving leg; grouped: config 4; "
                          "serve: config 5 at its full duration")
     ap.add_argument("--groups", type=int, default=512)
@@ -268,6 +308,16 @@ def main():
                                 "N(0,0.02) BF16, BF16 out, HBM budget %d GiB"
                                 % (args.serve_rate, args.serve_seconds, args.serve_budget_gb)},
             serving=res, **common)), flush=True)
+        return
+    if args.workload == "offgrid":
+        res = run_offgrid(args, sg, torch, ctx, stream)
+        print(json.dumps(dict(
+            metric="off-grid mean BF16 TFLOPs: DP pad/split dispatch vs naive pad-to-tile",
+            value=res["dp_split_pad"]["mean_tflops"], unit="TFLOPs", higher_is_better=True,
+            ms_per_step=res["dp_split_pad"]["total_s"] * 1e3,
+            config={"workload": "4096 BF16 NN GEMMs, M,N,K ~ U{1..8192} (seed 3), uniform[-1,1] "
+                                "BF16 inputs, FP32 accumulate, BF16 out"},
+            offgrid=res, **common)), flush=True)
         return
     if args.workload == "grouped":
         if args.table:

@@ -172,7 +172,7 @@ int sg_table_values(const sg_table* t, int which, double* out, int64_t n);
 int sg_table_variants(const sg_table* t, int* ids, int cap, int* nvar);
 /* Number of leaves (kernel launches, split-K reductions not counted) the plan of (M,N,K) runs. */
 int sg_table_plan_leaves(const sg_table* t, int64_t M, int64_t N, int64_t K, int* out_leaves);
-/* Binary file with a fingerprint (device name, compute-unit count, HIP runtime version, grid,
+/* Binary file with a fingerprint (GPU architecture, compute-unit count, HIP runtime version, grid,
  * variant set, output type); load refuses a mismatch with SG_EMISMATCH unless `force` != 0.
  * Loading requires the current HIP device only when force == 0. */
 int sg_table_save(const sg_table* t, const char* path);

@@ -27,11 +27,23 @@
 
 #include "sg_internal.h"
 #include "tile_body.h"
+#include "tile_body_dma.h"
 
 namespace sg {
 
 const TileShape kTiles[kNumTiles] = {{256, 256}, {256, 128}, {128, 256}, {128, 128},
                                      {128, 64},  {64, 128},  {64, 64}};
+
+// Aligned fast path with direct-to-LDS operand loads (see tile_body_dma.h).
+template <int BM, int BN>
+__global__ __launch_bounds__(256) void sg_gemm_tile_dma(KArgs p) {
+    __shared__ __attribute__((aligned(1024))) uint16_t smem[dma_smem_bytes<BM, BN>() / 2];
+    int tm, tn;
+    tile_coords(p.tiles_m, p.tiles_n, tm, tn);
+    const int m0 = tm * BM, n0 = tn * BN;
+    if (m0 >= p.M || n0 >= p.N) return;            // padding-only tile
+    tile_body_dma<BM, BN>(p, m0, n0, blockIdx.z, smem);
+}
 
 template <int BM, int BN, bool ALIGNED>
 __global__ __launch_bounds__(256) void sg_gemm_tile(KArgs p) {
@@ -122,9 +134,12 @@ static int launch_tile(const LaunchDesc& d, int variant, void* ws, hipStream_t s
     if (nwg > 0x7FFFFFFF) return fail(SG_EINVAL, "launch grid too large");
     dim3 grid((unsigned)nwg, 1, (unsigned)S), block(256);
     hipEvent_t stop1 = (S > 1) ? nullptr : d.ev_stop;
-    if (aligned)
-        hipExtLaunchKernelGGL((sg_gemm_tile<BM, BN, true>), grid, block, 0, stream, d.ev_start, stop1, 0, a);
-    else
+    if (aligned) {
+        if constexpr (dma_tile<BM, BN>())
+            hipExtLaunchKernelGGL((sg_gemm_tile_dma<BM, BN>), grid, block, 0, stream, d.ev_start, stop1, 0, a);
+        else
+            hipExtLaunchKernelGGL((sg_gemm_tile<BM, BN, true>), grid, block, 0, stream, d.ev_start, stop1, 0, a);
+    } else
         hipExtLaunchKernelGGL((sg_gemm_tile<BM, BN, false>), grid, block, 0, stream, d.ev_start, stop1, 0, a);
     SG_HIP(hipGetLastError());
     if (S > 1) {

@@ -15,15 +15,20 @@
 
 #include "sg_internal.h"
 #include "tile_body.h"
+#include "tile_body_dma.h"
 
 namespace sg {
 
 
-template <int BM, int BN>
+// ALL_ALIGNED: every problem of the launch takes the aligned fast path, so the kernel does not
+// carry the element-wise fallback body (fewer registers, more resident work-groups).
+template <int BM, int BN, bool ALL_ALIGNED>
 __global__ __launch_bounds__(256) void sg_gemm_grouped(const GroupProblem* __restrict__ probs, int G,
                                                         int total_tiles, int out_bf16,
                                                         int* __restrict__ counters) {
-    __shared__ __attribute__((aligned(16))) uint16_t smem[smem_elems<BM, BN>()];
+    constexpr int kSmem = dma_tile<BM, BN>() && dma_smem_bytes<BM, BN>() / 2 > smem_elems<BM, BN>()
+                              ? dma_smem_bytes<BM, BN>() / 2 : smem_elems<BM, BN>();
+    __shared__ __attribute__((aligned(1024))) uint16_t smem[kSmem];
     __shared__ int s_tile;
     for (;;) {
         __syncthreads();                       // previous tile done with the LDS and s_tile
@@ -49,8 +54,12 @@ __global__ __launch_bounds__(256) void sg_gemm_grouped(const GroupProblem* __res
         a.out_bf16 = out_bf16; a.add_kind = ADD_NONE;
         a.vec_ok = q.vec_ok;
         a.a_bytes = q.a_bytes; a.b_bytes = q.b_bytes;
-        if (q.aligned) tile_body<BM, BN, true>(a, tm * BM, tn * BN, 0, smem);
-        else tile_body<BM, BN, false>(a, tm * BM, tn * BN, 0, smem);
+        if (ALL_ALIGNED || q.aligned) {
+            if constexpr (dma_tile<BM, BN>()) tile_body_dma<BM, BN>(a, tm * BM, tn * BN, 0, smem);
+            else tile_body<BM, BN, true>(a, tm * BM, tn * BN, 0, smem);
+        } else {
+            if constexpr (!ALL_ALIGNED) tile_body<BM, BN, false>(a, tm * BM, tn * BN, 0, smem);
+        }
     }
     if (threadIdx.x == 0) {
         __threadfence();
@@ -64,25 +73,31 @@ __global__ __launch_bounds__(256) void sg_gemm_grouped(const GroupProblem* __res
 
 typedef void (*GroupedKernel)(const GroupProblem*, int, int, int, int*);
 
-static GroupedKernel grouped_kernel(int tile) {
+template <bool AA>
+static GroupedKernel grouped_kernel_t(int tile) {
     switch (tile) {
-        case 0: return sg_gemm_grouped<256, 256>;
-        case 1: return sg_gemm_grouped<256, 128>;
-        case 2: return sg_gemm_grouped<128, 256>;
-        case 3: return sg_gemm_grouped<128, 128>;
-        case 4: return sg_gemm_grouped<128, 64>;
-        case 5: return sg_gemm_grouped<64, 128>;
-        default: return sg_gemm_grouped<64, 64>;
+        case 0: return sg_gemm_grouped<256, 256, AA>;
+        case 1: return sg_gemm_grouped<256, 128, AA>;
+        case 2: return sg_gemm_grouped<128, 256, AA>;
+        case 3: return sg_gemm_grouped<128, 128, AA>;
+        case 4: return sg_gemm_grouped<128, 64, AA>;
+        case 5: return sg_gemm_grouped<64, 128, AA>;
+        default: return sg_gemm_grouped<64, 64, AA>;
     }
 }
 
+static GroupedKernel grouped_kernel(int tile, bool all_aligned) {
+    return all_aligned ? grouped_kernel_t<true>(tile) : grouped_kernel_t<false>(tile);
+}
+
 int grouped_fill(const sg_problem* probs, int G, int tile, int c_dtype, bool lpt, GroupProblem* out,
-                 int* order, int* total_tiles, double* flops) {
+                 int* order, int* total_tiles, double* flops, bool* all_aligned) {
     const TileShape ts = kTiles[tile];
     std::iota(order, order + G, 0);
     if (lpt) std::stable_sort(order, order + G, [&](int a, int b) { return probs[a].K > probs[b].K; });
     int64_t tiles = 0;
     double fl = 0.0;
+    bool aa = true;
     const size_t esz = c_dtype == SG_BF16 ? 2 : 4;
     for (int i = 0; i < G; ++i) {
         const sg_problem& q = probs[order[i]];
@@ -98,6 +113,7 @@ int grouped_fill(const sg_problem* probs, int G, int tile, int c_dtype, bool lpt
                         (uintptr_t)q.A % 16 == 0 && (uintptr_t)q.B % 16 == 0 && ab < 0x7FFFFFFF &&
                         bb < 0x7FFFFFFF;
         g.aligned = al ? 1 : 0;
+        aa = aa && al;
         g.a_bytes = al ? (int)ab : 0;
         g.b_bytes = al ? (int)bb : 0;
         g.vec_ok = (q.ldc % 4 == 0 && (uintptr_t)q.C % (4 * esz) == 0) ? 1 : 0;
@@ -107,12 +123,13 @@ int grouped_fill(const sg_problem* probs, int G, int tile, int c_dtype, bool lpt
     }
     *total_tiles = (int)tiles;
     *flops = fl;
+    *all_aligned = aa;
     return SG_OK;
 }
 
-int grouped_grid(int tile, int device, int total_tiles, int grid_wgs, int* grid) {
+int grouped_grid(int tile, bool all_aligned, int device, int total_tiles, int grid_wgs, int* grid) {
     int per_cu = 1, cus = 0;
-    SG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, grouped_kernel(tile), 256, 0));
+    SG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, grouped_kernel(tile, all_aligned), 256, 0));
     SG_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device));
     int g = std::max(1, per_cu) * cus;
     if (grid_wgs > 0) g = grid_wgs;
@@ -120,9 +137,10 @@ int grouped_grid(int tile, int device, int total_tiles, int grid_wgs, int* grid)
     return SG_OK;
 }
 
-int grouped_enqueue(int tile, const GroupProblem* d_probs, int G, int total_tiles, int grid,
-                    int c_dtype, int* d_counters, hipStream_t s, hipEvent_t start, hipEvent_t stop) {
-    hipExtLaunchKernelGGL(grouped_kernel(tile), dim3(grid), dim3(256), 0, s, start, stop, 0, d_probs, G,
+int grouped_enqueue(int tile, bool all_aligned, const GroupProblem* d_probs, int G, int total_tiles,
+                    int grid, int c_dtype, int* d_counters, hipStream_t s, hipEvent_t start,
+                    hipEvent_t stop) {
+    hipExtLaunchKernelGGL(grouped_kernel(tile, all_aligned), dim3(grid), dim3(256), 0, s, start, stop, 0, d_probs, G,
                           total_tiles, c_dtype == SG_BF16 ? 1 : 0, d_counters);
     SG_HIP(hipGetLastError());
     return SG_OK;
@@ -139,6 +157,7 @@ struct sg_group_plan {
     sg_group_cfg cfg{};
     int total_tiles = 0;
     int grid = 0;
+    bool all_aligned = false;
     double flops = 0.0;
     std::vector<sg_problem> probs;    // host copy, in queue order
     GroupProblem* d_probs = nullptr;
@@ -170,19 +189,20 @@ int plan_upload(sg_group_plan* pl, const sg_problem* probs, hipStream_t s) {
     std::vector<GroupProblem> h(G);
     std::vector<int> order(G);
     int rc = grouped_fill(probs, G, pl->cfg.tile, pl->c_dtype, pl->cfg.order == 0, h.data(),
-                          order.data(), &pl->total_tiles, &pl->flops);
+                          order.data(), &pl->total_tiles, &pl->flops, &pl->all_aligned);
     if (rc) return rc;
     pl->probs.resize(G);
     for (int i = 0; i < G; ++i) pl->probs[i] = probs[order[i]];
     if (!pl->d_probs) SG_HIP(hipMalloc(&pl->d_probs, sizeof(GroupProblem) * G));
     SG_HIP(hipMemcpyAsync(pl->d_probs, h.data(), sizeof(GroupProblem) * G, hipMemcpyHostToDevice, s));
     SG_HIP(hipStreamSynchronize(s));
-    return grouped_grid(pl->cfg.tile, pl->device, pl->total_tiles, pl->cfg.grid_wgs, &pl->grid);
+    return grouped_grid(pl->cfg.tile, pl->all_aligned, pl->device, pl->total_tiles, pl->cfg.grid_wgs,
+                        &pl->grid);
 }
 
 int plan_enqueue(sg_group_plan* pl, hipStream_t s, hipEvent_t start = nullptr, hipEvent_t stop = nullptr) {
-    return grouped_enqueue(pl->cfg.tile, pl->d_probs, pl->G, pl->total_tiles, pl->grid, pl->c_dtype,
-                           pl->d_counters, s, start, stop);
+    return grouped_enqueue(pl->cfg.tile, pl->all_aligned, pl->d_probs, pl->G, pl->total_tiles, pl->grid,
+                           pl->c_dtype, pl->d_counters, s, start, stop);
 }
 
 }  // namespace

@@ -242,15 +242,16 @@ bool worker_pass(sg_server* sv) {
         if (sv->cfg.mode == SG_SERVE_GROUPED) {
             int total = 0, grid = 0;
             double fl = 0;
+            bool aa = false;
             std::vector<int> order(group.size());
             rc = grouped_fill(probs.data(), (int)probs.size(), sv->cfg.tile, SG_BF16, true, sl.h_desc,
-                              order.data(), &total, &fl);
-            if (rc == SG_OK) rc = grouped_grid(sv->cfg.tile, sv->device, total, 0, &grid);
+                              order.data(), &total, &fl, &aa);
+            if (rc == SG_OK) rc = grouped_grid(sv->cfg.tile, aa, sv->device, total, 0, &grid);
             if (rc == SG_OK && hipMemcpyAsync(sl.d_desc, sl.h_desc, sizeof(GroupProblem) * probs.size(),
                                               hipMemcpyHostToDevice, sl.s) != hipSuccess)
                 rc = SG_EHIP;
             if (rc == SG_OK)
-                rc = grouped_enqueue(sv->cfg.tile, sl.d_desc, (int)probs.size(), total, grid, SG_BF16,
+                rc = grouped_enqueue(sv->cfg.tile, aa, sl.d_desc, (int)probs.size(), total, grid, SG_BF16,
                                      sl.d_counters, sl.s, nullptr, nullptr);
         } else {
             const sg_problem& q = probs[0];

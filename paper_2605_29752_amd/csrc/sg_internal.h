@@ -76,14 +76,16 @@ struct GroupProblem {
 // Grouped launch building blocks (also used by the server, which stages descriptors itself).
 // Fill host descriptors for tile shape `tile`; order[i] receives the caller's index of queue
 // entry i (longest K first when lpt, else as given).
+// *all_aligned: every problem can take the aligned fast path.
 int grouped_fill(const sg_problem* probs, int G, int tile, int c_dtype, bool lpt, GroupProblem* out,
-                 int* order, int* total_tiles, double* flops);
+                 int* order, int* total_tiles, double* flops, bool* all_aligned);
 // Resident work-groups for the tile shape on `device` (capped at the tile count).
-int grouped_grid(int tile, int device, int total_tiles, int grid_wgs, int* grid);
+int grouped_grid(int tile, bool all_aligned, int device, int total_tiles, int grid_wgs, int* grid);
 // Enqueue one persistent launch over device descriptors; counters: 2 ints, zero before the
 // first launch, returned to zero by every launch.
-int grouped_enqueue(int tile, const GroupProblem* d_probs, int G, int total_tiles, int grid,
-                    int c_dtype, int* d_counters, hipStream_t s, hipEvent_t start, hipEvent_t stop);
+int grouped_enqueue(int tile, bool all_aligned, const GroupProblem* d_probs, int G, int total_tiles,
+                    int grid, int c_dtype, int* d_counters, hipStream_t s, hipEvent_t start,
+                    hipEvent_t stop);
 
 // Device generator launcher.
 int launch_fill(uint16_t* dst, int64_t n, uint64_t seed, uint64_t stream_id, int64_t offset,

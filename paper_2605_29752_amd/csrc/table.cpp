@@ -116,7 +116,7 @@ static std::string device_fingerprint(int* cus, int* rt) {
     if (hipGetDeviceProperties(&p, dev) != hipSuccess) return "unknown";
     *cus = p.multiProcessorCount;
     (void)hipRuntimeGetVersion(rt);
-    return std::string(p.name) + "|" + p.gcnArchName;
+    return std::string(p.gcnArchName);   // the marketing name is not stable (profilers blank it)
 }
 
 }  // namespace sg

@@ -74,6 +74,89 @@ struct Stage {
 template <int BM, int BN>
 constexpr int smem_elems() { return 2 * (BM + BN) * LDK; }
 
+// Epilogue shared by both tile bodies.  Each wave stages one 16-row band of its C sub-tile at
+// a time in its own LDS slice (the caller's main loop ended with a barrier, so the operand
+// stages are free), then writes the band out row by row: lanes cover 4 consecutive columns
+// each, so a wave stores whole row segments.  acc[i][j] holds rows 16 i + (lane % 16) and
+// columns 16 j + 4 (lane / 16) .. + 3 of the wave's sub-tile.
+template <int BM, int BN>
+__device__ __forceinline__ void epilogue(const KArgs& p, const int m0, const int n0, const int kz,
+                                         uint16_t* __restrict__ smem,
+                                         const f32x4_t (&acc)[BM / 32][BN / 32]) {
+    constexpr int WM = BM / 2, WN = BN / 2;
+    constexpr int FM = WM / 16, FN = WN / 16;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int lr = lane & 15, lg = lane >> 4;
+    constexpr int EPAD = WN + 4;                          // f32 row of the band, padded
+    float* band = (float*)smem + wave * 16 * EPAD;
+    const int64_t zoff = (int64_t)kz * p.ws_slice;
+    constexpr int COLS4 = WN / 4;                         // 4-column groups per band row
+    constexpr int ROWS_PER_PASS = 64 / COLS4;             // band rows written per pass
+#pragma unroll
+    for (int i = 0; i < FM; ++i) {
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+            *(f32x4_t*)(band + lr * EPAD + j * 16 + lg * 4) = acc[i][j];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const int mb = m0 + wm * WM + i * 16;
+        const int nbase = n0 + wn * WN + (lane % COLS4) * 4;
+#pragma unroll 1
+        for (int r = lane / COLS4; r < 16; r += ROWS_PER_PASS) {
+            const int m = mb + r;
+            const int n = nbase;
+            if (m >= p.M || n >= p.N) continue;
+            f32x4_t v = *(const f32x4_t*)(band + r * EPAD + (lane % COLS4) * 4);
+            const bool full = p.vec_ok && (n + 3 < p.N);
+            if (p.add_kind == ADD_F32) {
+                const float* ap = (const float*)p.add + (int64_t)m * p.ldadd + n;
+                if (full) {
+                    v += *(const f32x4_t*)ap;
+                } else {
+                    for (int e = 0; e < 4; ++e)
+                        if (n + e < p.N) v[e] += ap[e];
+                }
+            } else if (p.add_kind == ADD_BF16) {
+                const uint16_t* ap = (const uint16_t*)p.add + (int64_t)m * p.ldadd + n;
+                if (full) {
+                    const u32x2_t a2 = *(const u32x2_t*)ap;
+                    v[0] += bf16_to_f32(a2[0] & 0xFFFFu); v[1] += bf16_to_f32(a2[0] >> 16);
+                    v[2] += bf16_to_f32(a2[1] & 0xFFFFu); v[3] += bf16_to_f32(a2[1] >> 16);
+                } else {
+                    for (int e = 0; e < 4; ++e)
+                        if (n + e < p.N) v[e] += bf16_to_f32(ap[e]);
+                }
+            }
+            if (p.out_bf16) {
+                uint16_t* cp = (uint16_t*)p.C + zoff + (int64_t)m * p.ldc + n;
+                if (full) {
+                    u32x2_t o;
+                    o[0] = (uint32_t)f32_to_bf16_rne(v[0]) | ((uint32_t)f32_to_bf16_rne(v[1]) << 16);
+                    o[1] = (uint32_t)f32_to_bf16_rne(v[2]) | ((uint32_t)f32_to_bf16_rne(v[3]) << 16);
+                    *(u32x2_t*)cp = o;
+                } else {
+                    for (int e = 0; e < 4; ++e)
+                        if (n + e < p.N) cp[e] = f32_to_bf16_rne(v[e]);
+                }
+            } else {
+                float* cp = (float*)p.C + zoff + (int64_t)m * p.ldc + n;
+                if (full) {
+                    *(f32x4_t*)cp = v;
+                } else {
+                    for (int e = 0; e < 4; ++e)
+                        if (n + e < p.N) cp[e] = v[e];
+                }
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+}
+
 // One BM x BN tile of C at (m0, n0) over the K range of split kz.  Called by all 256 threads of
 // a work-group; smem holds smem_elems<BM, BN>() elements.
 template <int BM, int BN, bool ALIGNED>
@@ -278,77 +361,8 @@ __device__ __forceinline__ void tile_body(const KArgs& p, const int m0, const in
         }
     }
 
-    // ---- epilogue ------------------------------------------------------------------------------
-    // Each wave stages one 16-row band of its C sub-tile at a time in its own LDS slice (the
-    // main loop ended with a barrier, so the operand stages are free), then writes the band out
-    // row by row: lanes cover 4 consecutive columns each, so a wave stores whole row segments.
-    constexpr int EPAD = WN + 4;                          // f32 row of the band, padded
-    static_assert(4 * 16 * EPAD * 4 <= 2 * STAGE * 2, "epilogue staging must fit the LDS");
-    float* band = (float*)smem + wave * 16 * EPAD;
-    const int64_t zoff = (int64_t)kz * p.ws_slice;
-    constexpr int COLS4 = WN / 4;                         // 4-column groups per band row
-    constexpr int ROWS_PER_PASS = 64 / COLS4;             // band rows written per pass
-#pragma unroll
-    for (int i = 0; i < FM; ++i) {
-#pragma unroll
-        for (int j = 0; j < FN; ++j)
-            *(f32x4_t*)(band + lr * EPAD + j * 16 + lg * 4) = acc[i][j];
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        const int mb = m0 + wm * WM + i * 16;
-        const int nbase = n0 + wn * WN + (lane % COLS4) * 4;
-#pragma unroll 1
-        for (int r = lane / COLS4; r < 16; r += ROWS_PER_PASS) {
-            const int m = mb + r;
-            const int n = nbase;
-            if (m >= p.M || n >= p.N) continue;
-            f32x4_t v = *(const f32x4_t*)(band + r * EPAD + (lane % COLS4) * 4);
-            const bool full = p.vec_ok && (n + 3 < p.N);
-            if (p.add_kind == ADD_F32) {
-                const float* ap = (const float*)p.add + (int64_t)m * p.ldadd + n;
-                if (full) {
-                    v += *(const f32x4_t*)ap;
-                } else {
-                    for (int e = 0; e < 4; ++e)
-                        if (n + e < p.N) v[e] += ap[e];
-                }
-            } else if (p.add_kind == ADD_BF16) {
-                const uint16_t* ap = (const uint16_t*)p.add + (int64_t)m * p.ldadd + n;
-                if (full) {
-                    const u32x2_t a2 = *(const u32x2_t*)ap;
-                    v[0] += bf16_to_f32(a2[0] & 0xFFFFu); v[1] += bf16_to_f32(a2[0] >> 16);
-                    v[2] += bf16_to_f32(a2[1] & 0xFFFFu); v[3] += bf16_to_f32(a2[1] >> 16);
-                } else {
-                    for (int e = 0; e < 4; ++e)
-                        if (n + e < p.N) v[e] += bf16_to_f32(ap[e]);
-                }
-            }
-            if (p.out_bf16) {
-                uint16_t* cp = (uint16_t*)p.C + zoff + (int64_t)m * p.ldc + n;
-                if (full) {
-                    u32x2_t o;
-                    o[0] = (uint32_t)f32_to_bf16_rne(v[0]) | ((uint32_t)f32_to_bf16_rne(v[1]) << 16);
-                    o[1] = (uint32_t)f32_to_bf16_rne(v[2]) | ((uint32_t)f32_to_bf16_rne(v[3]) << 16);
-                    *(u32x2_t*)cp = o;
-                } else {
-                    for (int e = 0; e < 4; ++e)
-                        if (n + e < p.N) cp[e] = f32_to_bf16_rne(v[e]);
-                }
-            } else {
-                float* cp = (float*)p.C + zoff + (int64_t)m * p.ldc + n;
-                if (full) {
-                    *(f32x4_t*)cp = v;
-                } else {
-                    for (int e = 0; e < 4; ++e)
-                        if (n + e < p.N) cp[e] = v[e];
-                }
-            }
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    }
+    static_assert(4 * 16 * (WN + 4) * 4 <= 2 * STAGE * 2, "epilogue staging must fit the LDS");
+    epilogue<BM, BN>(p, m0, n0, kz, smem, acc);
 }
 
 }  // namespace sg

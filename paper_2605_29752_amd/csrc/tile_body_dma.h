@@ -1,0 +1,191 @@
+// Tile body with direct-to-LDS operand loads (aligned fast path).
+//
+// The same tile as tile_body.h (256 threads, 2 x 2 waves, MFMA 16x16x32 BF16, B^T as the
+// first MFMA operand, LDS-staged epilogue), but the operands travel HBM -> LDS with
+// `buffer_load_dwordx4 ... lds`: no staging registers, so the loads of three K steps can be in
+// flight at once in a ring of four LDS stages (32-deep K steps).
+//
+// LDS layout per stage (no padding: one DMA instruction writes 1 KiB contiguously):
+//  * A: BM rows x 32 BF16 (64 B), the four 16-byte chunks of row r stored at slot
+//    chunk ^ ((r >> 2) & 3), so the 16 rows of a fragment read fall in 16 distinct 4-bank groups;
+//  * B: 32 rows (K) x BN BF16 (N contiguous, as in HBM), the 16-byte chunk c of row k stored
+//    at slot c ^ swz(k), swz(k) = (2 (k & 3)) ^ (8 ((k >> 3) & 3)) (within the row's chunks).
+//    A B fragment (8 consecutive K at one N per lane) comes from two ds_read_b64_tr_b16: within
+//    each 16-lane group, result[i][e] is element i % 4 of the 4 elements at the address given by
+//    lane 4 e + i / 4, so lane j of group g points at B[8 g + j / 4 (+ 4)][n0 + 4 (j % 4)] and
+//    receives column n0 + j at K rows 8 g .. 8 g + 7.  The swizzle puts the four K rows one read
+//    touches, and the four groups, in distinct 16-byte slots.
+// Out-of-range elements are fetched with an offset past the end of the buffer and land as zeros.
+#pragma once
+
+#include "tile_body.h"
+
+namespace sg {
+
+template <int BM, int BN>
+struct DmaTile {
+    static constexpr int BKD = 32;                       // K per stage
+    static constexpr int STAGES = 4;
+    static constexpr int A_BYTES = BM * BKD * 2;
+    static constexpr int B_BYTES = BKD * BN * 2;
+    static constexpr int STAGE_BYTES = A_BYTES + B_BYTES;
+    static constexpr int A_INSTR = A_BYTES / 1024 / 4;   // DMA instructions per wave per stage
+    static constexpr int B_INSTR = B_BYTES / 1024 / 4;
+    static constexpr int B_ROWS_PER_INSTR = 512 / BN;    // 1 KiB = 512 BF16
+    static constexpr int B_CHUNKS = BN / 8;              // 16-byte chunks per B row
+    static constexpr int LDS_BYTES = STAGES * STAGE_BYTES;
+    static_assert(A_INSTR >= 1 && B_INSTR >= 1 && B_CHUNKS >= 8, "tile shape");
+};
+
+// Which aligned tiles take the direct-to-LDS body.  The 256-wide tiles keep the register-staged
+// body: they run one work-group per CU either way, and their 64-deep K step (twice the MFMA work
+// per barrier) measures faster than four 32-deep stages.
+template <int BM, int BN>
+constexpr bool dma_tile() { return BM * BN <= 128 * 128; }
+
+template <int BM, int BN>
+constexpr int dma_smem_bytes() {
+    constexpr int ring = DmaTile<BM, BN>::LDS_BYTES;
+    constexpr int epi = 4 * 16 * (BN / 2 + 4) * 4;
+    return ring > epi ? ring : epi;
+}
+
+// s_waitcnt with only the vector-memory counter constrained (gfx9 encoding: vmcnt in bits 3:0
+// and 15:14, expcnt 6:4 and lgkmcnt 11:8 left at their maxima).
+template <int N>
+__device__ __forceinline__ void wait_vmcnt() {
+    static_assert(N >= 0 && N < 64, "vmcnt");
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_waitcnt((N & 0xF) | ((N >> 4) << 14) | (0x7 << 4) | (0xF << 8));
+    asm volatile("" ::: "memory");
+}
+
+typedef __attribute__((address_space(3))) void lds_void;
+typedef __bf16 bf16x4_t __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) bf16x4_t lds_bf16x4;
+
+template <int BM, int BN>
+__device__ __forceinline__ void tile_body_dma(const KArgs& p, const int m0, const int n0, const int kz,
+                                              uint16_t* __restrict__ smem) {
+    using T = DmaTile<BM, BN>;
+    constexpr int WM = BM / 2, WN = BN / 2;
+    constexpr int FM = WM / 16, FN = WN / 16;
+    constexpr int PER_STAGE = T::A_INSTR + T::B_INSTR;  // vmcnt units per stage per lane
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int lr = lane & 15, lg = lane >> 4;
+
+    const int kb = kz * p.k_chunk;
+    const int ke = min(p.Kl, kb + p.k_chunk);
+    const int nk = (ke - kb + T::BKD - 1) / T::BKD;
+
+    constexpr uint32_t kOut = 0x80000000u;
+    const __amdgpu_buffer_rsrc_t rA = __builtin_amdgcn_make_buffer_rsrc((void*)p.A, (short)0, p.a_bytes, 0x00020000);
+    const __amdgpu_buffer_rsrc_t rB = __builtin_amdgcn_make_buffer_rsrc((void*)p.B, (short)0, p.b_bytes, 0x00020000);
+    lds_void* lds = (lds_void*)smem;
+
+    // Per-lane DMA geometry (fixed over the loop).
+    // A instruction i of this wave covers tile rows 16 q .. 16 q + 15, q = wave * A_INSTR + i;
+    // lane -> row 16 q + lane / 4, slot lane % 4, which holds chunk slot ^ ((row >> 2) & 3).
+    const int a_row0 = lane >> 2;
+    const int a_slot = lane & 3;
+    // B instruction i covers K rows q * R .. q * R + R - 1, q = wave * B_INSTR + i.
+    const int b_row0 = lane / T::B_CHUNKS;
+    const int b_slot = lane % T::B_CHUNKS;
+    auto b_swz = [](int k) { return ((2 * (k & 3)) ^ (8 * ((k >> 3) & 3))) & (T::B_CHUNKS - 1); };
+
+    typedef __attribute__((address_space(3))) char lds_char;
+    const int wave_u = __builtin_amdgcn_readfirstlane(wave);   // DMA destinations are per wave
+    auto issue = [&](int kt, int slot) {
+        const int k0 = kb + kt * T::BKD;
+        const int stage = slot * T::STAGE_BYTES;           // LDS byte offset of the stage
+#pragma unroll
+        for (int i = 0; i < T::A_INSTR; ++i) {
+            const int q = wave_u * T::A_INSTR + i;
+            const int row = q * 16 + a_row0;
+            const int chunk = a_slot ^ ((row >> 2) & 3);
+            const bool ok = (m0 + row < p.M) && (k0 + chunk * 8 < p.K);
+            uint32_t o = ok ? (uint32_t)(((int64_t)(m0 + row) * p.lda + k0 + chunk * 8) * 2) : kOut;
+            asm volatile("" : "+v"(o));
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                rA, (lds_void*)((lds_char*)lds + stage + q * 1024), 16,
+                (int)o, 0, 0, 0);
+        }
+#pragma unroll
+        for (int i = 0; i < T::B_INSTR; ++i) {
+            const int q = wave_u * T::B_INSTR + i;
+            const int row = q * T::B_ROWS_PER_INSTR + b_row0;
+            const int chunk = b_slot ^ b_swz(row);
+            const bool ok = (k0 + row < p.K) && (n0 + chunk * 8 < p.N);
+            uint32_t o = ok ? (uint32_t)(((int64_t)(k0 + row) * p.ldb + n0 + chunk * 8) * 2) : kOut;
+            asm volatile("" : "+v"(o));
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                rB, (lds_void*)((lds_char*)lds + stage + T::A_BYTES + q * 1024), 16,
+                (int)o, 0, 0, 0);
+        }
+    };
+
+    f32x4_t acc[FM][FN];
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) acc[i][j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+
+    auto compute = [&](int slot) {
+        const char* stage = (const char*)smem + slot * T::STAGE_BYTES;
+        bf16x8_t af[FM], bfr[FN];
+#pragma unroll
+        for (int i = 0; i < FM; ++i) {
+            const int row = wm * WM + i * 16 + lr;
+            af[i] = *(const bf16x8_t*)(stage + row * 64 + ((lg ^ ((row >> 2) & 3)) << 4));
+        }
+        const int tk = lg * 8 + (lr >> 2);               // K row this lane points at (+4: second read)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
+            const int n = wn * WN + j * 16 + 4 * (lr & 3);  // first of 4 columns this lane points at
+            bf16x4_t h[2];
+#pragma unroll
+            for (int r = 0; r < 2; ++r) {
+                const int k = tk + 4 * r;
+                const int off = T::A_BYTES + k * BN * 2 + (((n >> 3) ^ b_swz(k)) << 4) + (n & 7) * 2;
+                h[r] = __builtin_amdgcn_ds_read_tr16_b64_v4bf16(
+                    (lds_bf16x4*)((lds_char*)lds + slot * T::STAGE_BYTES + off));
+            }
+            bfr[j] = bf16x8_t{h[0][0], h[0][1], h[0][2], h[0][3], h[1][0], h[1][1], h[1][2], h[1][3]};
+        }
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int j = 0; j < FN; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bfr[j], af[i], acc[i][j], 0, 0, 0);
+    };
+
+    // prologue: stages 0 .. S-2 in flight
+#pragma unroll
+    for (int s = 0; s < T::STAGES - 1; ++s)
+        if (s < nk) issue(s, s);
+    for (int kt = 0; kt < nk; ++kt) {
+        // this wave's loads of step kt have landed once at most min(nk-1, kt+S-2) - kt later
+        // steps' loads are still outstanding
+        const int later = min(nk - 1, kt + T::STAGES - 2) - kt;
+        if (later >= 2) wait_vmcnt<2 * PER_STAGE>();
+        else if (later == 1) wait_vmcnt<PER_STAGE>();
+        else wait_vmcnt<0>();
+        // Every wave's step kt has landed and every wave has consumed step kt-1 (its fragment
+        // reads fed its MFMAs before it got here).  A bare barrier: __syncthreads() would add a
+        // fence that waits for all outstanding DMA loads and empty the ring every step.  The
+        // empty asm statements keep the compiler from moving LDS accesses across it.
+        asm volatile("" ::: "memory");
+        __builtin_amdgcn_s_barrier();
+        asm volatile("" ::: "memory");
+        if (kt + T::STAGES - 1 < nk) issue(kt + T::STAGES - 1, (kt + T::STAGES - 1) % T::STAGES);
+        compute(kt % T::STAGES);
+    }
+    __syncthreads();                            // ring no longer read: the epilogue reuses it
+
+    epilogue<BM, BN>(p, m0, n0, kz, smem, acc);
+}
+
+}  // namespace sg
