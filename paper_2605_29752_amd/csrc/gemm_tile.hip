@@ -2,16 +2,15 @@
 //
 // C = A * B, A M x K row-major (K contiguous), B K x N row-major (N contiguous); the problem
 // statement of the paper's Sec. 2.2 / Sec. 7.1.  Each work-group (256 threads = 4 wave64 in a
-// 2 x 2 arrangement) computes one BM x BN tile of C over a 64-deep K step:
+// 2 x 2 arrangement) computes one BM x BN tile of C with v_mfma_f32_16x16x32_bf16 and FP32
+// accumulators in registers.  Two bodies:
 //
-//  * global -> registers: A in 16-byte chunks along K; B in 8-row x (BN/32)-column blocks so
-//    that every thread can transpose its block in registers (B must reach the matrix cores
-//    K-contiguous, but it is stored N-contiguous);
-//  * registers -> LDS: both operands stored K-contiguous, rows padded to 72 elements
-//    (144 bytes) so 16 consecutive rows of a fragment read hit 16 disjoint 4-bank groups;
-//  * LDS -> matrix cores: v_mfma_f32_16x16x32_bf16, FP32 accumulators in registers;
-//  * two LDS stages: the next K step's global loads are in flight while the current one is
-//    multiplied, one barrier per K step.
+//  * aligned operands (leading dimensions, K and N multiples of 8, 16-byte bases: every shape
+//    of the landscape): tile_body_dma.h, operands loaded HBM -> LDS directly into a ring of four
+//    32-deep K stages, three stages of loads in flight, B fragments read with transposing LDS
+//    reads;
+//  * anything else: tile_body.h, element-wise predicated loads into registers, B transposed in
+//    registers, two padded LDS stages of 64-deep K steps.
 //
 // The MFMA is issued with B^T as its first operand, so each lane ends up holding four
 // consecutive N columns of one C row and stores them as one vector.
@@ -45,14 +44,14 @@ __global__ __launch_bounds__(256) void sg_gemm_tile_dma(KArgs p) {
     tile_body_dma<BM, BN>(p, m0, n0, blockIdx.z, smem);
 }
 
-template <int BM, int BN, bool ALIGNED>
+template <int BM, int BN>
 __global__ __launch_bounds__(256) void sg_gemm_tile(KArgs p) {
     __shared__ __attribute__((aligned(16))) uint16_t smem[smem_elems<BM, BN>()];
     int tm, tn;
     tile_coords(p.tiles_m, p.tiles_n, tm, tn);
     const int m0 = tm * BM, n0 = tn * BN;
     if (m0 >= p.M || n0 >= p.N) return;            // padding-only tile
-    tile_body<BM, BN, ALIGNED>(p, m0, n0, blockIdx.z, smem);
+    tile_body<BM, BN>(p, m0, n0, blockIdx.z, smem);
 }
 
 // Fixed-order sum of S FP32 partial slices (M x N, ld = N) plus the epilogue.
@@ -134,13 +133,10 @@ static int launch_tile(const LaunchDesc& d, int variant, void* ws, hipStream_t s
     if (nwg > 0x7FFFFFFF) return fail(SG_EINVAL, "launch grid too large");
     dim3 grid((unsigned)nwg, 1, (unsigned)S), block(256);
     hipEvent_t stop1 = (S > 1) ? nullptr : d.ev_stop;
-    if (aligned) {
-        if constexpr (dma_tile<BM, BN>())
-            hipExtLaunchKernelGGL((sg_gemm_tile_dma<BM, BN>), grid, block, 0, stream, d.ev_start, stop1, 0, a);
-        else
-            hipExtLaunchKernelGGL((sg_gemm_tile<BM, BN, true>), grid, block, 0, stream, d.ev_start, stop1, 0, a);
-    } else
-        hipExtLaunchKernelGGL((sg_gemm_tile<BM, BN, false>), grid, block, 0, stream, d.ev_start, stop1, 0, a);
+    if (aligned)
+        hipExtLaunchKernelGGL((sg_gemm_tile_dma<BM, BN>), grid, block, 0, stream, d.ev_start, stop1, 0, a);
+    else
+        hipExtLaunchKernelGGL((sg_gemm_tile<BM, BN>), grid, block, 0, stream, d.ev_start, stop1, 0, a);
     SG_HIP(hipGetLastError());
     if (S > 1) {
         const int64_t total = d.M * d.N;

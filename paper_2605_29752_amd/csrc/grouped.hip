@@ -26,7 +26,8 @@ template <int BM, int BN, bool ALL_ALIGNED>
 __global__ __launch_bounds__(256) void sg_gemm_grouped(const GroupProblem* __restrict__ probs, int G,
                                                         int total_tiles, int out_bf16,
                                                         int* __restrict__ counters) {
-    constexpr int kSmem = dma_tile<BM, BN>() && dma_smem_bytes<BM, BN>() / 2 > smem_elems<BM, BN>()
+    // the aligned body's ring, or the larger of it and the element-wise body's stages
+    constexpr int kSmem = (ALL_ALIGNED || dma_smem_bytes<BM, BN>() / 2 > smem_elems<BM, BN>())
                               ? dma_smem_bytes<BM, BN>() / 2 : smem_elems<BM, BN>();
     __shared__ __attribute__((aligned(1024))) uint16_t smem[kSmem];
     __shared__ int s_tile;
@@ -55,10 +56,9 @@ __global__ __launch_bounds__(256) void sg_gemm_grouped(const GroupProblem* __res
         a.vec_ok = q.vec_ok;
         a.a_bytes = q.a_bytes; a.b_bytes = q.b_bytes;
         if (ALL_ALIGNED || q.aligned) {
-            if constexpr (dma_tile<BM, BN>()) tile_body_dma<BM, BN>(a, tm * BM, tn * BN, 0, smem);
-            else tile_body<BM, BN, true>(a, tm * BM, tn * BN, 0, smem);
+            tile_body_dma<BM, BN>(a, tm * BM, tn * BN, 0, smem);
         } else {
-            if constexpr (!ALL_ALIGNED) tile_body<BM, BN, false>(a, tm * BM, tn * BN, 0, smem);
+            if constexpr (!ALL_ALIGNED) tile_body<BM, BN>(a, tm * BM, tn * BN, 0, smem);
         }
     }
     if (threadIdx.x == 0) {

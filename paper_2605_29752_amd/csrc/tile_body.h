@@ -157,21 +157,13 @@ __device__ __forceinline__ void epilogue(const KArgs& p, const int m0, const int
     }
 }
 
-// One BM x BN tile of C at (m0, n0) over the K range of split kz.  Called by all 256 threads of
-// a work-group; smem holds smem_elems<BM, BN>() elements.
-template <int BM, int BN, bool ALIGNED>
+// One BM x BN tile of C at (m0, n0) over the K range of split kz for operands that do not meet
+// the aligned path's conditions (odd leading dimensions, K or N not a multiple of 8, unaligned
+// bases): element-wise predicated loads into registers, then LDS.  Called by all 256 threads
+// of a work-group; smem holds smem_elems<BM, BN>() elements.
+template <int BM, int BN>
 __device__ __forceinline__ void tile_body(const KArgs& p, const int m0, const int n0, const int kz,
                                           uint16_t* __restrict__ smem) {
-#ifndef SG_DEPTH_LARGE
-#define SG_DEPTH_LARGE 1
-#endif
-#ifndef SG_DEPTH_SMALL
-#define SG_DEPTH_SMALL 1
-#endif
-    // K steps of global loads in flight.  One for every tile: a second register staging set
-    // spills the tiles of 256 x 128 and up, and halves the resident work-groups of the smaller
-    // ones, which then no longer hide each other's latency.
-    constexpr int DEPTH = (BM * BN >= 256 * 128) ? SG_DEPTH_LARGE : SG_DEPTH_SMALL;
     constexpr int WM = BM / 2, WN = BN / 2;        // per-wave tile
     constexpr int FM = WM / 16, FN = WN / 16;      // MFMA fragments per wave
     constexpr int A_CHUNKS = Stage<BM, BN>::A_CHUNKS;
@@ -193,75 +185,32 @@ __device__ __forceinline__ void tile_body(const KArgs& p, const int m0, const in
     const int nb = tid >> 3;                       // B column block
     const int gn = n0 + nb * NB;
 
-    // Buffer resources: a read whose byte offset is at or past num_records returns zero, so
-    // out-of-range elements are predicated without branches by moving their offset out.
-    constexpr uint32_t kOut = 0x80000000u;
-    const __amdgpu_buffer_rsrc_t rA = __builtin_amdgcn_make_buffer_rsrc((void*)p.A, (short)0, p.a_bytes, 0x00020000);
-    const __amdgpu_buffer_rsrc_t rB = __builtin_amdgcn_make_buffer_rsrc((void*)p.B, (short)0, p.b_bytes, 0x00020000);
-    // One per-lane base offset per operand; chunk, row and step offsets are uniform (scalar)
-    // strides added on the fly, so no per-chunk offsets occupy registers across the loop.
-    const int rowb = tid >> 3;                     // A row of chunk 0 within the tile
-    const int mrem = p.M - m0;                     // valid A rows of this tile
-    const uint32_t baseA = (uint32_t)(((int64_t)(m0 + rowb) * p.lda + kb + c * 8) * 2);
-    const uint32_t baseB = (uint32_t)(((int64_t)(kb + c * 8) * p.ldb + gn) * 2);
-    const uint32_t rowStrideA = (uint32_t)(32 * p.lda * 2);   // 32 rows between A chunks
-    const uint32_t rowStrideB = (uint32_t)(p.ldb * 2);
-    const bool colB = gn < p.N;
-
     auto load = [&](Stage<BM, BN>& s, int kt) {
         const int k0 = kb + kt * kBK;
-        if constexpr (ALIGNED) {
-            const bool kA = k0 + c * 8 < p.K;      // K % 8 == 0: a chunk is wholly in or out
-            const uint32_t stepA = (uint32_t)(kt * kBK * 2);
 #pragma unroll
-            for (int i = 0; i < A_CHUNKS; ++i) {
-                const bool ok = kA && (rowb + 32 * i < mrem);
-                uint32_t o = ok ? baseA + (uint32_t)i * rowStrideA + stepA : kOut;
-                asm volatile("" : "+v"(o));        // keep the select: no load duplicated per branch
-                s.a[i] = __builtin_bit_cast(u32x4_t, __builtin_amdgcn_raw_buffer_load_b128(rA, (int)o, 0, 0));
+        for (int i = 0; i < A_CHUNKS; ++i) {
+            const int gm = m0 + ((tid + i * 256) >> 3), gk = k0 + c * 8;
+            const uint16_t* rowp = p.A + (int64_t)gm * p.lda;
+            uint32_t w[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int k_lo = gk + 2 * e, k_hi = k_lo + 1;
+                uint32_t lo = (gm < p.M && k_lo < p.K) ? rowp[k_lo] : 0u;
+                uint32_t hi = (gm < p.M && k_hi < p.K) ? rowp[k_hi] : 0u;
+                w[e] = lo | (hi << 16);
             }
-            const uint32_t stepB = (uint32_t)(kt * kBK) * rowStrideB;
+            s.a[i] = u32x4_t{w[0], w[1], w[2], w[3]};
+        }
 #pragma unroll
-            for (int r = 0; r < 8; ++r) {
-                const bool ok = colB && (k0 + c * 8 + r < p.K);
-                uint32_t o = ok ? baseB + stepB + (uint32_t)r * rowStrideB : kOut;
-                asm volatile("" : "+v"(o));
-                if constexpr (NB == 8) {
-                    u32x4_t v = __builtin_bit_cast(u32x4_t, __builtin_amdgcn_raw_buffer_load_b128(rB, (int)o, 0, 0));
-                    s.b[r][0] = v[0]; s.b[r][1] = v[1]; s.b[r][2] = v[2]; s.b[r][3] = v[3];
-                } else if constexpr (NB == 4) {
-                    u32x2_t v = __builtin_bit_cast(u32x2_t, __builtin_amdgcn_raw_buffer_load_b64(rB, (int)o, 0, 0));
-                    s.b[r][0] = v[0]; s.b[r][1] = v[1];
-                } else {
-                    s.b[r][0] = __builtin_amdgcn_raw_buffer_load_b32(rB, (int)o, 0, 0);
-                }
-            }
-        } else {
+        for (int r = 0; r < 8; ++r) {
+            const int gk = k0 + c * 8 + r;
+            const uint16_t* src = p.B + (int64_t)gk * p.ldb + gn;
 #pragma unroll
-            for (int i = 0; i < A_CHUNKS; ++i) {
-                const int gm = m0 + ((tid + i * 256) >> 3), gk = k0 + c * 8;
-                const uint16_t* rowp = p.A + (int64_t)gm * p.lda;
-                uint32_t w[4];
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const int k_lo = gk + 2 * e, k_hi = k_lo + 1;
-                    uint32_t lo = (gm < p.M && k_lo < p.K) ? rowp[k_lo] : 0u;
-                    uint32_t hi = (gm < p.M && k_hi < p.K) ? rowp[k_hi] : 0u;
-                    w[e] = lo | (hi << 16);
-                }
-                s.a[i] = u32x4_t{w[0], w[1], w[2], w[3]};
-            }
-#pragma unroll
-            for (int r = 0; r < 8; ++r) {
-                const int gk = k0 + c * 8 + r;
-                const uint16_t* src = p.B + (int64_t)gk * p.ldb + gn;
-#pragma unroll
-                for (int w = 0; w < NB / 2; ++w) {
-                    const int n_lo = gn + 2 * w, n_hi = n_lo + 1;
-                    uint32_t lo = (gk < p.K && n_lo < p.N) ? src[2 * w] : 0u;
-                    uint32_t hi = (gk < p.K && n_hi < p.N) ? src[2 * w + 1] : 0u;
-                    s.b[r][w] = lo | (hi << 16);
-                }
+            for (int w = 0; w < NB / 2; ++w) {
+                const int n_lo = gn + 2 * w, n_hi = n_lo + 1;
+                uint32_t lo = (gk < p.K && n_lo < p.N) ? src[2 * w] : 0u;
+                uint32_t hi = (gk < p.K && n_hi < p.N) ? src[2 * w + 1] : 0u;
+                s.b[r][w] = lo | (hi << 16);
             }
         }
     };
@@ -321,44 +270,19 @@ __device__ __forceinline__ void tile_body(const KArgs& p, const int m0, const in
         }
     };
 
-    // Pipeline: the global loads of step kt+2 are in flight while step kt is multiplied and
-    // step kt+1 (loaded one step earlier) is written to the other LDS stage.
-    // Large tiles (DEPTH 1) hold one staging set: their MFMA work per step already covers the
-    // load latency, and a second set would not fit the register file.
-    if constexpr (DEPTH == 2) {
-        Stage<BM, BN> s0, s1;
-        if (nk > 0) load(s0, 0);
-        if (nk > 1) load(s1, 1);
-        if (nk > 0) store(s0, 0);
+    // Pipeline: the loads of step kt+1 are in flight while step kt is multiplied, then they are
+    // written to the other LDS stage.
+    Stage<BM, BN> s0;
+    if (nk > 0) {
+        load(s0, 0);
+        store(s0, 0);
+    }
+    __syncthreads();
+    for (int kt = 0; kt < nk; ++kt) {
+        if (kt + 1 < nk) load(s0, kt + 1);
+        compute(kt & 1);
+        if (kt + 1 < nk) store(s0, (kt + 1) & 1);
         __syncthreads();
-        for (int kt = 0; kt < nk; kt += 2) {
-            if (kt + 2 < nk) load(s0, kt + 2);
-            __builtin_amdgcn_sched_barrier(0);     // keep the two halves' schedules apart
-            compute(0);
-            __builtin_amdgcn_sched_barrier(0);
-            if (kt + 1 < nk) store(s1, 1);
-            __syncthreads();
-            if (kt + 1 >= nk) break;
-            if (kt + 3 < nk) load(s1, kt + 3);
-            __builtin_amdgcn_sched_barrier(0);
-            compute(1);
-            __builtin_amdgcn_sched_barrier(0);
-            if (kt + 2 < nk) store(s0, 0);
-            __syncthreads();
-        }
-    } else {
-        Stage<BM, BN> s0;
-        if (nk > 0) {
-            load(s0, 0);
-            store(s0, 0);
-        }
-        __syncthreads();
-        for (int kt = 0; kt < nk; ++kt) {
-            if (kt + 1 < nk) load(s0, kt + 1);
-            compute(kt & 1);
-            if (kt + 1 < nk) store(s0, (kt + 1) & 1);
-            __syncthreads();
-        }
     }
 
     static_assert(4 * 16 * (WN + 4) * 4 <= 2 * STAGE * 2, "epilogue staging must fit the LDS");

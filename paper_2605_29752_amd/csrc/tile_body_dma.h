@@ -37,12 +37,6 @@ struct DmaTile {
     static_assert(A_INSTR >= 1 && B_INSTR >= 1 && B_CHUNKS >= 8, "tile shape");
 };
 
-// Which aligned tiles take the direct-to-LDS body.  The 256-wide tiles keep the register-staged
-// body: they run one work-group per CU either way, and their 64-deep K step (twice the MFMA work
-// per barrier) measures faster than four 32-deep stages.
-template <int BM, int BN>
-constexpr bool dma_tile() { return BM * BN <= 128 * 128; }
-
 template <int BM, int BN>
 constexpr int dma_smem_bytes() {
     constexpr int ring = DmaTile<BM, BN>::LDS_BYTES;
@@ -63,6 +57,39 @@ __device__ __forceinline__ void wait_vmcnt() {
 typedef __attribute__((address_space(3))) void lds_void;
 typedef __bf16 bf16x4_t __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(3))) bf16x4_t lds_bf16x4;
+typedef int i32x4_t __attribute__((ext_vector_type(4)));
+
+// Raw buffer resource over [base, base + bytes): stride 0, so the range check is offset < bytes
+// and an out-of-range load returns zeros.
+__device__ __forceinline__ i32x4_t dma_rsrc(const void* base, uint32_t bytes) {
+    const uint64_t a = (uint64_t)base;
+    i32x4_t r;
+    r.x = __builtin_amdgcn_readfirstlane((int)(uint32_t)a);
+    r.y = __builtin_amdgcn_readfirstlane((int)(uint32_t)(a >> 32) & 0xFFFF);
+    r.z = __builtin_amdgcn_readfirstlane((int)bytes);
+    r.w = 0x00020000;
+    return r;
+}
+
+// One 16-byte-per-lane load from a buffer straight into LDS: lane i writes 16 bytes at LDS byte
+// address lds + 16 i.  Written as inline asm on purpose: the compiler's wait-count pass cannot
+// tell which ring stage a direct-to-LDS load writes, and for the builtin it waits for every
+// outstanding load before each later LDS read, which drains the ring on every K step.  Here
+// the loop's own counted waits and barrier order the LDS reads after the data lands.  The asm
+// restores M0, which the compiler treats as its own; the load has no register result, so
+// nothing is left in flight towards a register the compiler could reuse.
+__device__ __forceinline__ void dma16(const i32x4_t rsrc, uint32_t voffset, uint32_t lds) {
+    int saved;
+    asm volatile(
+        "s_mov_b32 %0, m0\n\t"
+        "s_mov_b32 m0, %3\n\t"
+        "s_nop 0\n\t"
+        "buffer_load_dwordx4 %1, %2, 0 offen lds\n\t"
+        "s_mov_b32 m0, %0"
+        : "=&s"(saved)
+        : "v"(voffset), "s"(rsrc), "s"(lds)
+        : "memory");
+}
 
 template <int BM, int BN>
 __device__ __forceinline__ void tile_body_dma(const KArgs& p, const int m0, const int n0, const int kz,
@@ -82,9 +109,10 @@ __device__ __forceinline__ void tile_body_dma(const KArgs& p, const int m0, cons
     const int nk = (ke - kb + T::BKD - 1) / T::BKD;
 
     constexpr uint32_t kOut = 0x80000000u;
-    const __amdgpu_buffer_rsrc_t rA = __builtin_amdgcn_make_buffer_rsrc((void*)p.A, (short)0, p.a_bytes, 0x00020000);
-    const __amdgpu_buffer_rsrc_t rB = __builtin_amdgcn_make_buffer_rsrc((void*)p.B, (short)0, p.b_bytes, 0x00020000);
+    const i32x4_t rA = dma_rsrc(p.A, p.a_bytes);
+    const i32x4_t rB = dma_rsrc(p.B, p.b_bytes);
     lds_void* lds = (lds_void*)smem;
+    const uint32_t lds_base = (uint32_t)(uintptr_t)lds;
 
     // Per-lane DMA geometry (fixed over the loop).
     // A instruction i of this wave covers tile rows 16 q .. 16 q + 15, q = wave * A_INSTR + i;
@@ -109,9 +137,7 @@ __device__ __forceinline__ void tile_body_dma(const KArgs& p, const int m0, cons
             const bool ok = (m0 + row < p.M) && (k0 + chunk * 8 < p.K);
             uint32_t o = ok ? (uint32_t)(((int64_t)(m0 + row) * p.lda + k0 + chunk * 8) * 2) : kOut;
             asm volatile("" : "+v"(o));
-            __builtin_amdgcn_raw_ptr_buffer_load_lds(
-                rA, (lds_void*)((lds_char*)lds + stage + q * 1024), 16,
-                (int)o, 0, 0, 0);
+            dma16(rA, o, lds_base + stage + q * 1024);
         }
 #pragma unroll
         for (int i = 0; i < T::B_INSTR; ++i) {
@@ -121,9 +147,7 @@ __device__ __forceinline__ void tile_body_dma(const KArgs& p, const int m0, cons
             const bool ok = (k0 + row < p.K) && (n0 + chunk * 8 < p.N);
             uint32_t o = ok ? (uint32_t)(((int64_t)(k0 + row) * p.ldb + n0 + chunk * 8) * 2) : kOut;
             asm volatile("" : "+v"(o));
-            __builtin_amdgcn_raw_ptr_buffer_load_lds(
-                rB, (lds_void*)((lds_char*)lds + stage + T::A_BYTES + q * 1024), 16,
-                (int)o, 0, 0, 0);
+            dma16(rB, o, lds_base + stage + T::A_BYTES + q * 1024);
         }
     };
 
