@@ -126,26 +126,47 @@ __device__ __forceinline__ void tile_body_dma(const KArgs& p, const int m0, cons
 
     typedef __attribute__((address_space(3))) char lds_char;
     const int wave_u = __builtin_amdgcn_readfirstlane(wave);   // DMA destinations are per wave
+
+    // Per-lane byte offsets of step 0, or kOut where the lane's row (A) or column chunk (B) lies
+    // outside the data.  A later step adds a uniform stride; kOut plus any in-range stride stays
+    // at or above 2^31, past every readable extent, so such lanes keep loading zeros.
+    uint32_t a_off[T::A_INSTR], b_off[T::B_INSTR];
+#pragma unroll
+    for (int i = 0; i < T::A_INSTR; ++i) {
+        const int row = (wave_u * T::A_INSTR + i) * 16 + a_row0;
+        const int chunk = a_slot ^ ((row >> 2) & 3);
+        a_off[i] = (m0 + row < p.M) ? (uint32_t)(((int64_t)(m0 + row) * p.lda + kb + chunk * 8) * 2) : kOut;
+    }
+#pragma unroll
+    for (int i = 0; i < T::B_INSTR; ++i) {
+        const int row = (wave_u * T::B_INSTR + i) * T::B_ROWS_PER_INSTR + b_row0;
+        const int chunk = b_slot ^ b_swz(row);
+        b_off[i] = (n0 + chunk * 8 < p.N) ? (uint32_t)(((int64_t)(kb + row) * p.ldb + n0 + chunk * 8) * 2) : kOut;
+    }
+    const uint32_t a_step = T::BKD * 2;                          // bytes per K step
+    const uint32_t b_step = (uint32_t)(T::BKD * p.ldb * 2);
+
     auto issue = [&](int kt, int slot) {
         const int k0 = kb + kt * T::BKD;
         const int stage = slot * T::STAGE_BYTES;           // LDS byte offset of the stage
+        // Whole step inside K (every step but a ragged last one): no per-lane depth check.
+        const bool interior = k0 + T::BKD <= p.K;
 #pragma unroll
         for (int i = 0; i < T::A_INSTR; ++i) {
             const int q = wave_u * T::A_INSTR + i;
-            const int row = q * 16 + a_row0;
-            const int chunk = a_slot ^ ((row >> 2) & 3);
-            const bool ok = (m0 + row < p.M) && (k0 + chunk * 8 < p.K);
-            uint32_t o = ok ? (uint32_t)(((int64_t)(m0 + row) * p.lda + k0 + chunk * 8) * 2) : kOut;
+            uint32_t o = a_off[i] + (uint32_t)kt * a_step;
+            if (!interior) {
+                const int chunk = a_slot ^ (((q * 16 + a_row0) >> 2) & 3);
+                if (k0 + chunk * 8 >= p.K) o = kOut;
+            }
             asm volatile("" : "+v"(o));
             dma16(rA, o, lds_base + stage + q * 1024);
         }
 #pragma unroll
         for (int i = 0; i < T::B_INSTR; ++i) {
             const int q = wave_u * T::B_INSTR + i;
-            const int row = q * T::B_ROWS_PER_INSTR + b_row0;
-            const int chunk = b_slot ^ b_swz(row);
-            const bool ok = (k0 + row < p.K) && (n0 + chunk * 8 < p.N);
-            uint32_t o = ok ? (uint32_t)(((int64_t)(k0 + row) * p.ldb + n0 + chunk * 8) * 2) : kOut;
+            uint32_t o = b_off[i] + (uint32_t)kt * b_step;
+            if (!interior && k0 + q * T::B_ROWS_PER_INSTR + b_row0 >= p.K) o = kOut;
             asm volatile("" : "+v"(o));
             dma16(rB, o, lds_base + stage + T::A_BYTES + q * 1024);
         }
