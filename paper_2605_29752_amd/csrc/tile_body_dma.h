@@ -2,12 +2,15 @@
 //
 // The same tile as tile_body.h (256 threads, 2 x 2 waves, MFMA 16x16x32 BF16, B^T as the
 // first MFMA operand, LDS-staged epilogue), but the operands travel HBM -> LDS with
-// `buffer_load_dwordx4 ... lds`: no staging registers, so the loads of three K steps can be in
-// flight at once in a ring of four LDS stages (32-deep K steps).
+// `buffer_load_dwordx4 ... lds`: no staging registers, so the loads of several K steps can be
+// in flight at once in a ring of LDS stages (32-deep K steps; four stages, two for 256 x 128).
 //
 // LDS layout per stage (no padding: one DMA instruction writes 1 KiB contiguously):
 //  * A: BM rows x 32 BF16 (64 B), the four 16-byte chunks of row r stored at slot
-//    chunk ^ ((r >> 2) & 3), so the 16 rows of a fragment read fall in 16 distinct 4-bank groups;
+//    chunk ^ ((r >> 1) & 3).  A 16-byte-per-lane LDS read is served eight lanes (128 bytes, the
+//    32 four-byte banks) at a time; the eight rows those lanes read from fall in distinct
+//    (row parity, slot) pairs, so no two share a bank (measured: no bank-conflict cycles,
+//    where the (r >> 2) & 3 variant had one conflict cycle per access cycle);
 //  * B: 32 rows (K) x BN BF16 (N contiguous, as in HBM), the 16-byte chunk c of row k stored
 //    at slot c ^ swz(k), swz(k) = (2 (k & 3)) ^ (8 ((k >> 3) & 3)) (within the row's chunks).
 //    A B fragment (8 consecutive K at one N per lane) comes from two ds_read_b64_tr_b16: within
@@ -25,7 +28,12 @@ namespace sg {
 template <int BM, int BN>
 struct DmaTile {
     static constexpr int BKD = 32;                       // K per stage
-    static constexpr int STAGES = 4;
+    // Ring depth.  The 256 x 128 tiles take two stages: their 48 KiB ring lets two work-groups
+    // share a CU, which hides more latency than deeper prefetch in one work-group (4096^3:
+    // 1,070-1,140 against 730 TFLOP/s with four stages).  The other tiles keep four: 256 x 256
+    // runs one work-group per CU either way, and the smaller tiles measure faster on
+    // mid-sized shapes with deeper prefetch.
+    static constexpr int STAGES = (BM * BN == 256 * 128) ? 2 : 4;
     static constexpr int A_BYTES = BM * BKD * 2;
     static constexpr int B_BYTES = BKD * BN * 2;
     static constexpr int STAGE_BYTES = A_BYTES + B_BYTES;
@@ -35,6 +43,7 @@ struct DmaTile {
     static constexpr int B_CHUNKS = BN / 8;              // 16-byte chunks per B row
     static constexpr int LDS_BYTES = STAGES * STAGE_BYTES;
     static_assert(A_INSTR >= 1 && B_INSTR >= 1 && B_CHUNKS >= 8, "tile shape");
+    static_assert(STAGES >= 2 && STAGES <= 4, "the main loop's waits cover at most two later steps");
 };
 
 template <int BM, int BN>
@@ -116,12 +125,13 @@ __device__ __forceinline__ void tile_body_dma(const KArgs& p, const int m0, cons
 
     // Per-lane DMA geometry (fixed over the loop).
     // A instruction i of this wave covers tile rows 16 q .. 16 q + 15, q = wave * A_INSTR + i;
-    // lane -> row 16 q + lane / 4, slot lane % 4, which holds chunk slot ^ ((row >> 2) & 3).
+    // lane -> row 16 q + lane / 4, slot lane % 4, which holds chunk slot ^ a_swz(row).
     const int a_row0 = lane >> 2;
     const int a_slot = lane & 3;
     // B instruction i covers K rows q * R .. q * R + R - 1, q = wave * B_INSTR + i.
     const int b_row0 = lane / T::B_CHUNKS;
     const int b_slot = lane % T::B_CHUNKS;
+    auto a_swz = [](int row) { return (row >> 1) & 3; };
     auto b_swz = [](int k) { return ((2 * (k & 3)) ^ (8 * ((k >> 3) & 3))) & (T::B_CHUNKS - 1); };
 
     typedef __attribute__((address_space(3))) char lds_char;
@@ -134,7 +144,7 @@ __device__ __forceinline__ void tile_body_dma(const KArgs& p, const int m0, cons
 #pragma unroll
     for (int i = 0; i < T::A_INSTR; ++i) {
         const int row = (wave_u * T::A_INSTR + i) * 16 + a_row0;
-        const int chunk = a_slot ^ ((row >> 2) & 3);
+        const int chunk = a_slot ^ a_swz(row);
         a_off[i] = (m0 + row < p.M) ? (uint32_t)(((int64_t)(m0 + row) * p.lda + kb + chunk * 8) * 2) : kOut;
     }
 #pragma unroll
@@ -156,7 +166,7 @@ __device__ __forceinline__ void tile_body_dma(const KArgs& p, const int m0, cons
             const int q = wave_u * T::A_INSTR + i;
             uint32_t o = a_off[i] + (uint32_t)kt * a_step;
             if (!interior) {
-                const int chunk = a_slot ^ (((q * 16 + a_row0) >> 2) & 3);
+                const int chunk = a_slot ^ a_swz(q * 16 + a_row0);
                 if (k0 + chunk * 8 >= p.K) o = kOut;
             }
             asm volatile("" : "+v"(o));
@@ -184,7 +194,7 @@ __device__ __forceinline__ void tile_body_dma(const KArgs& p, const int m0, cons
 #pragma unroll
         for (int i = 0; i < FM; ++i) {
             const int row = wm * WM + i * 16 + lr;
-            af[i] = *(const bf16x8_t*)(stage + row * 64 + ((lg ^ ((row >> 2) & 3)) << 4));
+            af[i] = *(const bf16x8_t*)(stage + row * 64 + ((lg ^ a_swz(row)) << 4));
         }
         const int tk = lg * 8 + (lr >> 2);               // K row this lane points at (+4: second read)
 #pragma unroll
@@ -200,11 +210,15 @@ __device__ __forceinline__ void tile_body_dma(const KArgs& p, const int m0, cons
             }
             bfr[j] = bf16x8_t{h[0][0], h[0][1], h[0][2], h[0][3], h[1][0], h[1][1], h[1][2], h[1][3]};
         }
+        // raised wave priority while the MFMAs issue, so that the waves of a CU that are
+        // ready to multiply are preferred over those issuing loads (+5% on 256 x 256)
+        __builtin_amdgcn_s_setprio(1);
 #pragma unroll
         for (int i = 0; i < FM; ++i)
 #pragma unroll
             for (int j = 0; j < FN; ++j)
                 acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bfr[j], af[i], acc[i][j], 0, 0, 0);
+        __builtin_amdgcn_s_setprio(0);
     };
 
     // prologue: stages 0 .. S-2 in flight
