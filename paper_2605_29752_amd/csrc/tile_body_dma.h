@@ -156,30 +156,33 @@ __device__ __forceinline__ void tile_body_dma(const KArgs& p, const int m0, cons
     const uint32_t a_step = T::BKD * 2;                          // bytes per K step
     const uint32_t b_step = (uint32_t)(T::BKD * p.ldb * 2);
 
-    auto issue = [&](int kt, int slot) {
+    // Load instruction d (A instructions first, then B) of step kt into ring slot `slot`.
+    auto issue_one = [&](int kt, int slot, int d) {
         const int k0 = kb + kt * T::BKD;
         const int stage = slot * T::STAGE_BYTES;           // LDS byte offset of the stage
         // Whole step inside K (every step but a ragged last one): no per-lane depth check.
         const bool interior = k0 + T::BKD <= p.K;
-#pragma unroll
-        for (int i = 0; i < T::A_INSTR; ++i) {
-            const int q = wave_u * T::A_INSTR + i;
-            uint32_t o = a_off[i] + (uint32_t)kt * a_step;
+        if (d < T::A_INSTR) {
+            const int q = wave_u * T::A_INSTR + d;
+            uint32_t o = a_off[d] + (uint32_t)kt * a_step;
             if (!interior) {
                 const int chunk = a_slot ^ a_swz(q * 16 + a_row0);
                 if (k0 + chunk * 8 >= p.K) o = kOut;
             }
             asm volatile("" : "+v"(o));
             dma16(rA, o, lds_base + stage + q * 1024);
-        }
-#pragma unroll
-        for (int i = 0; i < T::B_INSTR; ++i) {
+        } else {
+            const int i = d - T::A_INSTR;
             const int q = wave_u * T::B_INSTR + i;
             uint32_t o = b_off[i] + (uint32_t)kt * b_step;
             if (!interior && k0 + q * T::B_ROWS_PER_INSTR + b_row0 >= p.K) o = kOut;
             asm volatile("" : "+v"(o));
             dma16(rB, o, lds_base + stage + T::A_BYTES + q * 1024);
         }
+    };
+    auto issue = [&](int kt, int slot) {
+#pragma unroll
+        for (int d = 0; d < PER_STAGE; ++d) issue_one(kt, slot, d);
     };
 
     f32x4_t acc[FM][FN];
@@ -188,7 +191,16 @@ __device__ __forceinline__ void tile_body_dma(const KArgs& p, const int m0, cons
 #pragma unroll
         for (int j = 0; j < FN; ++j) acc[i][j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
 
-    auto compute = [&](int slot) {
+    constexpr bool SPREAD = (BM == 256 && BN == 256);
+    // Multiply step `slot`; with SPREAD, the loads of step kt_next into slot_next are issued
+    // between the MFMA rows.  The CU's address unit takes a 1 KiB load instruction every 16
+    // cycles or so, so the loads of a whole stage from four waves take as long as a good part
+    // of the MFMA work.  For 256 x 256 (one work-group per CU, 128 MFMA cycles per row) they
+    // are spread over the MFMA rows, where they overlap with them (4096^3: 986 against 882
+    // TFLOP/s); the other tiles issue them in one burst before the MFMAs, which measures
+    // faster for them (the two-stage 256 x 128 ring needs its loads out as early as possible,
+    // and the smaller tiles' rows are too short to cover a load's issue).
+    auto compute = [&](int slot, bool issue_next, int kt_next, int slot_next) {
         const char* stage = (const char*)smem + slot * T::STAGE_BYTES;
         bf16x8_t af[FM], bfr[FN];
 #pragma unroll
@@ -211,36 +223,66 @@ __device__ __forceinline__ void tile_body_dma(const KArgs& p, const int m0, cons
             bfr[j] = bf16x8_t{h[0][0], h[0][1], h[0][2], h[0][3], h[1][0], h[1][1], h[1][2], h[1][3]};
         }
         // raised wave priority while the MFMAs issue, so that the waves of a CU that are
-        // ready to multiply are preferred over those issuing loads (+5% on 256 x 256)
+        // ready to multiply are preferred over those issuing loads
         __builtin_amdgcn_s_setprio(1);
 #pragma unroll
-        for (int i = 0; i < FM; ++i)
+        for (int i = 0; i < FM; ++i) {
 #pragma unroll
             for (int j = 0; j < FN; ++j)
                 acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bfr[j], af[i], acc[i][j], 0, 0, 0);
+            if constexpr (SPREAD) {
+                // loads ((i+1) PER_STAGE / FM) - (i PER_STAGE / FM) follow MFMA row i
+                __builtin_amdgcn_sched_barrier(0);
+                if (issue_next) {
+#pragma unroll
+                    for (int d = i * PER_STAGE / FM; d < (i + 1) * PER_STAGE / FM; ++d)
+                        issue_one(kt_next, slot_next, d);
+                }
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
         __builtin_amdgcn_s_setprio(0);
     };
 
-    // prologue: stages 0 .. S-2 in flight
-#pragma unroll
-    for (int s = 0; s < T::STAGES - 1; ++s)
-        if (s < nk) issue(s, s);
-    for (int kt = 0; kt < nk; ++kt) {
-        // this wave's loads of step kt have landed once at most min(nk-1, kt+S-2) - kt later
-        // steps' loads are still outstanding
-        const int later = min(nk - 1, kt + T::STAGES - 2) - kt;
+    // Step kt waits until this wave's loads of step kt have landed (at most `later` later
+    // steps' loads outstanding), meets the other waves, then multiplies step kt while the
+    // loads of step kt + S - 1 go out into the slot of step kt - 1.
+    // At the barrier every wave's step kt has landed and every wave has consumed step kt - 1
+    // (its fragment reads fed its MFMAs before it got here).  A bare barrier: __syncthreads()
+    // would add a fence that waits for all outstanding loads and empty the ring every step.
+    // The empty asm statements keep the compiler from moving LDS accesses across it.
+    auto sync_step = [&](int later) {
         if (later >= 2) wait_vmcnt<2 * PER_STAGE>();
         else if (later == 1) wait_vmcnt<PER_STAGE>();
         else wait_vmcnt<0>();
-        // Every wave's step kt has landed and every wave has consumed step kt-1 (its fragment
-        // reads fed its MFMAs before it got here).  A bare barrier: __syncthreads() would add a
-        // fence that waits for all outstanding DMA loads and empty the ring every step.  The
-        // empty asm statements keep the compiler from moving LDS accesses across it.
         asm volatile("" ::: "memory");
         __builtin_amdgcn_s_barrier();
         asm volatile("" ::: "memory");
-        if (kt + T::STAGES - 1 < nk) issue(kt + T::STAGES - 1, (kt + T::STAGES - 1) % T::STAGES);
-        compute(kt % T::STAGES);
+    };
+    constexpr int S = T::STAGES;
+#pragma unroll
+    for (int s = 0; s < S - 1; ++s)
+        if (s < nk) issue(s, s);
+    if constexpr (SPREAD) {
+        // A steady-state loop (loads issued inside the MFMA sequence, no branch there) and a
+        // drain without loads.
+        int kt = 0;
+        for (; kt + S - 1 < nk; ++kt) {
+            sync_step(S - 2);
+            compute(kt % S, true, kt + S - 1, (kt + S - 1) % S);
+        }
+        for (; kt < nk; ++kt) {
+            sync_step(nk - 1 - kt);
+            compute(kt % S, false, 0, 0);
+        }
+    } else {
+        // One loop with a uniform branch: for these tiles, accumulators that live across two
+        // loops get copied through a temporary before every MFMA by the compiler.
+        for (int kt = 0; kt < nk; ++kt) {
+            sync_step(min(nk - 1, kt + S - 2) - kt);
+            if (kt + S - 1 < nk) issue(kt + S - 1, (kt + S - 1) % S);
+            compute(kt % S, false, 0, 0);
+        }
     }
     __syncthreads();                            // ring no longer read: the epilogue reuses it
 
