@@ -72,6 +72,39 @@ __global__ __launch_bounds__(256) void sg_splitk_reduce(const float* ws, int64_t
     }
 }
 
+// The same, four consecutive columns per thread (N, ldc and ldadd multiples of 4, C and the
+// addend aligned to four elements): 16-byte partial loads, one index
+// division per four elements (launched for M * N / 4 < 2^30, so indices stay in int range).
+// Summation order and rounding are those of sg_splitk_reduce.
+__global__ __launch_bounds__(256) void sg_splitk_reduce4(const float* ws, int64_t slice, int S,
+                                                          int M, int N, void* C, int64_t ldc,
+                                                          int out_bf16, const void* add,
+                                                          int64_t ldadd, int add_kind) {
+    const int n4 = N >> 2;
+    const int total4 = M * n4;
+    for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < total4; q += gridDim.x * blockDim.x) {
+        const int m = q / n4, n = (q - m * n4) * 4;
+        const int64_t idx = (int64_t)m * N + n;
+        f32x4_t s = *(const f32x4_t*)(ws + idx);
+        for (int z = 1; z < S; ++z) s += *(const f32x4_t*)(ws + (int64_t)z * slice + idx);
+        if (add_kind == ADD_F32) {
+            s += *(const f32x4_t*)((const float*)add + (int64_t)m * ldadd + n);
+        } else if (add_kind == ADD_BF16) {
+            const u32x2_t a2 = *(const u32x2_t*)((const uint16_t*)add + (int64_t)m * ldadd + n);
+            s[0] += bf16_to_f32(a2[0] & 0xFFFFu); s[1] += bf16_to_f32(a2[0] >> 16);
+            s[2] += bf16_to_f32(a2[1] & 0xFFFFu); s[3] += bf16_to_f32(a2[1] >> 16);
+        }
+        if (out_bf16) {
+            u32x2_t o;
+            o[0] = (uint32_t)f32_to_bf16_rne(s[0]) | ((uint32_t)f32_to_bf16_rne(s[1]) << 16);
+            o[1] = (uint32_t)f32_to_bf16_rne(s[2]) | ((uint32_t)f32_to_bf16_rne(s[3]) << 16);
+            *(u32x2_t*)((uint16_t*)C + (int64_t)m * ldc + n) = o;
+        } else {
+            *(f32x4_t*)((float*)C + (int64_t)m * ldc + n) = s;
+        }
+    }
+}
+
 int lds_bytes_of_tile(int tile) {
     return 2 * (kTiles[tile].bm + kTiles[tile].bn) * LDK * (int)sizeof(uint16_t);
 }
@@ -115,6 +148,11 @@ static int launch_tile(const LaunchDesc& d, int variant, void* ws, hipStream_t s
                          a_bytes < 0x7FFFFFFF && b_bytes < 0x7FFFFFFF;
     a.a_bytes = aligned ? (int)a_bytes : 0;
     a.b_bytes = aligned ? (int)b_bytes : 0;
+    // 4-wide vector access to C and the addend
+    const size_t esz = d.out_bf16 ? 2 : 4;
+    bool vec_c = (d.ldc % 4 == 0) && ((uintptr_t)d.C % (4 * esz) == 0);
+    if (d.add_kind == ADD_F32) vec_c = vec_c && (d.ldadd % 4 == 0) && ((uintptr_t)d.add % 16 == 0);
+    if (d.add_kind == ADD_BF16) vec_c = vec_c && (d.ldadd % 4 == 0) && ((uintptr_t)d.add % 8 == 0);
     if (S > 1) {
         a.C = ws; a.ldc = d.N; a.ws_slice = d.M * d.N;
         a.out_bf16 = 0; a.add = nullptr; a.ldadd = 0; a.add_kind = ADD_NONE;
@@ -122,11 +160,7 @@ static int launch_tile(const LaunchDesc& d, int variant, void* ws, hipStream_t s
     } else {
         a.C = d.C; a.ldc = d.ldc; a.ws_slice = 0;
         a.out_bf16 = d.out_bf16; a.add = d.add; a.ldadd = d.ldadd; a.add_kind = d.add_kind;
-        const size_t esz = d.out_bf16 ? 2 : 4;
-        bool vec = (d.ldc % 4 == 0) && ((uintptr_t)d.C % (4 * esz) == 0);
-        if (d.add_kind == ADD_F32) vec = vec && (d.ldadd % 4 == 0) && ((uintptr_t)d.add % 16 == 0);
-        if (d.add_kind == ADD_BF16) vec = vec && (d.ldadd % 4 == 0) && ((uintptr_t)d.add % 8 == 0);
-        a.vec_ok = vec ? 1 : 0;
+        a.vec_ok = vec_c ? 1 : 0;
     }
     const int64_t nwg = (int64_t)a.tiles_m * a.tiles_n;
     if (nwg <= 0) return SG_OK;
@@ -140,11 +174,18 @@ static int launch_tile(const LaunchDesc& d, int variant, void* ws, hipStream_t s
     SG_HIP(hipGetLastError());
     if (S > 1) {
         const int64_t total = d.M * d.N;
-        int64_t blocks = (total + 255) / 256;
+        const bool vec4 = vec_c && (d.N % 4 == 0) && ((uintptr_t)ws % 16 == 0) && total / 4 < (1 << 30);
+        const int64_t items = vec4 ? total / 4 : total;
+        int64_t blocks = (items + 255) / 256;
         if (blocks > 65536) blocks = 65536;
-        hipExtLaunchKernelGGL(sg_splitk_reduce, dim3((unsigned)blocks), dim3(256), 0, stream,
-                              nullptr, d.ev_stop, 0, (const float*)ws, (int64_t)(d.M * d.N), S,
-                              (int)d.M, (int)d.N, d.C, d.ldc, d.out_bf16, d.add, d.ldadd, d.add_kind);
+        if (vec4)
+            hipExtLaunchKernelGGL(sg_splitk_reduce4, dim3((unsigned)blocks), dim3(256), 0, stream,
+                                  nullptr, d.ev_stop, 0, (const float*)ws, (int64_t)(d.M * d.N), S,
+                                  (int)d.M, (int)d.N, d.C, d.ldc, d.out_bf16, d.add, d.ldadd, d.add_kind);
+        else
+            hipExtLaunchKernelGGL(sg_splitk_reduce, dim3((unsigned)blocks), dim3(256), 0, stream,
+                                  nullptr, d.ev_stop, 0, (const float*)ws, (int64_t)(d.M * d.N), S,
+                                  (int)d.M, (int)d.N, d.C, d.ldc, d.out_bf16, d.add, d.ldadd, d.add_kind);
         SG_HIP(hipGetLastError());
     }
     return SG_OK;
