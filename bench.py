@@ -420,14 +420,22 @@ def main():
     stacks["best_single_%s" % sg.variant_info(best_single).name] = \
         stack_stats(sg, T0all[variants.index(best_single)], sizes)
 
-    # dominant kernel: the unsplit variant with the most kernel time (a split variant's launch
-    # time also covers its reduction kernel, so it is not one kernel's duration)
-    unsplit = np.array([sg.variant_info(v).splits == 1 for v in range(sg.num_variants())])
-    dom = int(np.argmax(np.where(unsplit, ksec, -1.0)))
-    vi = sg.variant_info(dom)
+    # dominant kernel: the tile kernel with the most execution time, over every variant that
+    # launches it (the split-K variants of a tile run the same kernel; their accounted time is
+    # the tile kernel's own, the reduction excluded)
+    tile_keys = sorted({(sg.variant_info(v).bm, sg.variant_info(v).bn) for v in range(sg.num_variants())})
+    tile_of = np.array([tile_keys.index((sg.variant_info(v).bm, sg.variant_info(v).bn))
+                        for v in range(sg.num_variants())])
+    ntiles = len(tile_keys)
+    t_sec = np.array([ksec[tile_of == t].sum() for t in range(ntiles)])
+    t_launch = np.array([launches[tile_of == t].sum() for t in range(ntiles)])
+    t_flops = np.array([kflops[tile_of == t].sum() for t in range(ntiles)])
+    dom_tile = int(np.argmax(t_sec))
+    vi = sg.variant_info(int(np.flatnonzero(tile_of == dom_tile)[0]))
     # every grid shape is aligned, so its tiles run the direct-to-LDS kernel
     dom_kernel = "sg_gemm_tile_dma<%d, %d>" % (vi.bm, vi.bn)
-    achieved = kflops[dom] / ksec[dom] / 1e12
+    achieved = t_flops[dom_tile] / t_sec[dom_tile] / 1e12
+    dom_variants = [sg.variant_info(v).name for v in np.flatnonzero((tile_of == dom_tile) & (launches > 0))]
     ex = stacks["dp_split_pad_executed"]
     plain = stacks["plain_%s" % sg.variant_info(args.plain_variant).name]
 
@@ -471,10 +479,10 @@ def main():
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_BF16_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_BF16_TFLOPS,
                      "traffic": traffic_bytes(dom_kernel),
-                     "kernel": dom_kernel, "variant": sg.variant_info(dom).name,
-                     "launches": int(launches[dom]),
-                     "avg_launch_us": ksec[dom] / max(launches[dom], 1) * 1e6,
-                     "flop_per_launch": kflops[dom] / max(launches[dom], 1)},
+                     "kernel": dom_kernel, "variants": dom_variants,
+                     "launches": int(t_launch[dom_tile]),
+                     "avg_launch_us": t_sec[dom_tile] / max(t_launch[dom_tile], 1) * 1e6,
+                     "flop_per_launch": t_flops[dom_tile] / max(t_launch[dom_tile], 1)},
         "device": props.name,
     }
     if not args.no_serve:

@@ -89,8 +89,10 @@ typedef struct sg_gemm_args {
 int gemm_bf16_nn_ex(sg_ctx* ctx, const sg_gemm_args* args, void* stream);
 
 /* ---- kernel variants (the tile family) ----------------------------------------------------
- * Variant v: tile BM x BN (64-deep K step, 256 threads, MFMA 16x16x32 BF16) and a parallel
- * split-K factor S (S > 1: FP32 partials in the workspace, then a fixed-order reduction). */
+ * Variant v: tile BM x BN (256 threads, MFMA 16x16x32 BF16) and a parallel split-K factor S
+ * (S > 1: FP32 partials in the workspace, then a fixed-order reduction).  bk is the K
+ * granularity of a split (64); lds_bytes is the LDS of the aligned kernel (its ring of 32-deep
+ * K stages). */
 typedef struct sg_variant_info {
     int id, bm, bn, bk, splits, threads;
     int lds_bytes;
@@ -125,8 +127,9 @@ int sg_sweep(sg_ctx* ctx, const sg_shape* shapes, int64_t n, int mode, int varia
              int warmup, int reps, const void* A_pool, const void* B_pool, void* C_pool,
              double* out_sec, void* stream);
 /* Per-variant launch accounting of the most recent sg_sweep on this context: for variant v,
- * launches[v] kernel launches took seconds[v] of kernel execution in total (timed runs only) and
- * did flops[v] algorithmic FLOP (2 M N K of the data shape of each launch). Arrays hold
+ * launches[v] tile-kernel launches took seconds[v] of tile-kernel execution in total (timed runs
+ * only; for split-K variants the reduction kernel that follows is not included) and did
+ * flops[v] algorithmic FLOP (2 M N K of the data shape of each launch). Arrays hold
  * sg_num_variants() entries. */
 int sg_sweep_kernel_times(const sg_ctx* ctx, int64_t* launches, double* seconds, double* flops);
 

@@ -105,8 +105,17 @@ __global__ __launch_bounds__(256) void sg_splitk_reduce4(const float* ws, int64_
     }
 }
 
+// LDS of the aligned (direct-to-LDS) kernel of a tile: its ring of K stages.
 int lds_bytes_of_tile(int tile) {
-    return 2 * (kTiles[tile].bm + kTiles[tile].bn) * LDK * (int)sizeof(uint16_t);
+    switch (tile) {
+        case 0: return dma_smem_bytes<256, 256>();
+        case 1: return dma_smem_bytes<256, 128>();
+        case 2: return dma_smem_bytes<128, 256>();
+        case 3: return dma_smem_bytes<128, 128>();
+        case 4: return dma_smem_bytes<128, 64>();
+        case 5: return dma_smem_bytes<64, 128>();
+        default: return dma_smem_bytes<64, 64>();
+    }
 }
 
 void split_geometry(int variant, int64_t Kl, int* splits, int64_t* k_chunk) {
@@ -119,12 +128,85 @@ void split_geometry(int variant, int64_t Kl, int* splits, int64_t* k_chunk) {
     *splits = (int)(s < 1 ? 1 : s);
 }
 
-size_t launch_workspace_bytes(int variant, const LaunchDesc& d) {
+// Zero-padded copy of a row-major BF16 matrix: dst[r][c] = src[r][c] for c < cols, 0 for
+// cols <= c < ldd (ldd a multiple of 8, rows * ldd < 2^31).  One 16-byte store per thread.
+__global__ __launch_bounds__(256) void sg_pack_bf16(const uint16_t* src, int64_t lds, int rows, int cols,
+                                                     uint16_t* dst, int ldd) {
+    const int n8 = ldd >> 3;
+    const int total = rows * n8;
+    for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < total; q += gridDim.x * blockDim.x) {
+        const int r = q / n8, c0 = (q - r * n8) * 8;
+        const uint16_t* sp = src + (int64_t)r * lds;
+        uint32_t w[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int c = c0 + 2 * e;
+            const uint32_t lo = c < cols ? sp[c] : 0u;
+            const uint32_t hi = c + 1 < cols ? sp[c + 1] : 0u;
+            w[e] = lo | (hi << 16);
+        }
+        *(u32x4_t*)(dst + (int64_t)r * ldd + c0) = u32x4_t{w[0], w[1], w[2], w[3]};
+    }
+}
+
+// Operands the direct-to-LDS kernel cannot read in place (leading dimension, K or N not a
+// multiple of 8, or a base not 16-byte aligned) are first copied to the workspace, zero-padded
+// to 8-element rows: A as M x roundup(K, 8), B as K x roundup(N, 8).  A chunk of 8 elements
+// that straddles the data edge then reads zeros beyond it, so the kernel's per-chunk checks
+// stay exact.  Layout in the workspace: split-K partials, then A', then B' (256-byte aligned).
+struct Packing {
+    bool pack_a = false, pack_b = false;
+    int64_t k8 = 0, n8 = 0;
+    size_t part_bytes = 0, a_off = 0, b_off = 0, total = 0;
+};
+
+static size_t round256(size_t x) { return (x + 255) & ~size_t(255); }
+
+static bool in_place_a(const LaunchDesc& d) {
+    return d.lda % 8 == 0 && d.K % 8 == 0 && (uintptr_t)d.A % 16 == 0;
+}
+static bool in_place_b(const LaunchDesc& d) {
+    return d.ldb % 8 == 0 && d.N % 8 == 0 && (uintptr_t)d.B % 16 == 0;
+}
+
+static Packing packing_of(int variant, const LaunchDesc& d) {
+    Packing pk;
     int S;
     int64_t kc;
     split_geometry(variant, d.Kl, &S, &kc);
-    if (S <= 1) return 0;
-    return (size_t)S * (size_t)d.M * (size_t)d.N * sizeof(float);
+    pk.part_bytes = S > 1 ? round256((size_t)S * (size_t)d.M * (size_t)d.N * sizeof(float)) : 0;
+    pk.total = pk.part_bytes;
+    if (d.K <= 0 || (in_place_a(d) && in_place_b(d))) return pk;
+    pk.k8 = (d.K + 7) / 8 * 8;
+    pk.n8 = (d.N + 7) / 8 * 8;
+    pk.pack_a = !in_place_a(d);
+    pk.pack_b = !in_place_b(d);
+    // every byte offset of the (packed or in-place) operands must fit the 31-bit buffer range
+    const int64_t a_ext = pk.pack_a ? d.M * pk.k8 * 2 : ((d.M - 1) * d.lda + d.K) * 2;
+    const int64_t b_ext = pk.pack_b ? d.K * pk.n8 * 2 : ((d.K - 1) * d.ldb + d.N) * 2;
+    if (a_ext >= 0x7FFFFFFF || b_ext >= 0x7FFFFFFF) {
+        pk.pack_a = pk.pack_b = false;                  // the element-wise body handles it
+        return pk;
+    }
+    pk.a_off = pk.total;
+    if (pk.pack_a) pk.total += round256((size_t)a_ext);
+    pk.b_off = pk.total;
+    if (pk.pack_b) pk.total += round256((size_t)b_ext);
+    return pk;
+}
+
+size_t launch_workspace_bytes(int variant, const LaunchDesc& d) { return packing_of(variant, d).total; }
+
+static int launch_pack(const uint16_t* src, int64_t lds, int64_t rows, int64_t cols, uint16_t* dst,
+                       int64_t ldd, hipEvent_t start, hipStream_t stream) {
+    const int64_t total = rows * (ldd / 8);
+    int64_t blocks = (total + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    if (blocks < 1) return SG_OK;
+    hipExtLaunchKernelGGL(sg_pack_bf16, dim3((unsigned)blocks), dim3(256), 0, stream, start, nullptr, 0,
+                          src, lds, (int)rows, (int)cols, dst, (int)ldd);
+    SG_HIP(hipGetLastError());
+    return SG_OK;
 }
 
 template <int BM, int BN>
@@ -139,12 +221,31 @@ static int launch_tile(const LaunchDesc& d, int variant, void* ws, hipStream_t s
     int64_t kc;
     split_geometry(variant, d.Kl, &S, &kc);
     a.k_chunk = (int)kc;
-    // Fast path: 16-byte chunks never straddle the data edge, and every valid byte offset fits
-    // the 31-bit range the buffer loads use.
-    const int64_t a_bytes = ((d.M - 1) * d.lda + d.K) * 2;
-    const int64_t b_bytes = (d.K > 0) ? ((d.K - 1) * d.ldb + d.N) * 2 : 0;
-    const bool aligned = (d.lda % 8 == 0) && (d.ldb % 8 == 0) && (d.K % 8 == 0) && (d.N % 8 == 0) &&
-                         ((uintptr_t)d.A % 16 == 0) && ((uintptr_t)d.B % 16 == 0) &&
+    // Direct-to-LDS path: 16-byte chunks never straddle the data edge (or, for a packed
+    // operand, straddle it into zeros), and every valid byte offset fits the 31-bit range the
+    // buffer loads use.  Otherwise the element-wise body.
+    const Packing pk = packing_of(variant, d);
+    hipEvent_t start = d.ev_start;                  // stamped by the launch's first kernel
+    if ((pk.pack_a || pk.pack_b) && ws != nullptr) {
+        if (pk.pack_a) {
+            uint16_t* ap = (uint16_t*)((char*)ws + pk.a_off);
+            int rc = launch_pack(d.A, d.lda, d.M, d.K, ap, pk.k8, start, stream);
+            if (rc) return rc;
+            start = nullptr;
+            a.A = ap; a.lda = pk.k8;
+        }
+        if (pk.pack_b) {
+            uint16_t* bp = (uint16_t*)((char*)ws + pk.b_off);
+            int rc = launch_pack(d.B, d.ldb, d.K, d.N, bp, pk.n8, start, stream);
+            if (rc) return rc;
+            start = nullptr;
+            a.B = bp; a.ldb = pk.n8;
+        }
+    }
+    const bool packed = (pk.pack_a || pk.pack_b) && ws != nullptr;
+    const int64_t a_bytes = pk.pack_a && packed ? d.M * pk.k8 * 2 : ((d.M - 1) * d.lda + d.K) * 2;
+    const int64_t b_bytes = d.K <= 0 ? 0 : pk.pack_b && packed ? d.K * pk.n8 * 2 : ((d.K - 1) * d.ldb + d.N) * 2;
+    const bool aligned = (packed || (in_place_a(d) && in_place_b(d))) &&
                          a_bytes < 0x7FFFFFFF && b_bytes < 0x7FFFFFFF;
     a.a_bytes = aligned ? (int)a_bytes : 0;
     a.b_bytes = aligned ? (int)b_bytes : 0;
@@ -153,7 +254,7 @@ static int launch_tile(const LaunchDesc& d, int variant, void* ws, hipStream_t s
     bool vec_c = (d.ldc % 4 == 0) && ((uintptr_t)d.C % (4 * esz) == 0);
     if (d.add_kind == ADD_F32) vec_c = vec_c && (d.ldadd % 4 == 0) && ((uintptr_t)d.add % 16 == 0);
     if (d.add_kind == ADD_BF16) vec_c = vec_c && (d.ldadd % 4 == 0) && ((uintptr_t)d.add % 8 == 0);
-    if (S > 1) {
+    if (S > 1) {                                   // partials at the workspace start
         a.C = ws; a.ldc = d.N; a.ws_slice = d.M * d.N;
         a.out_bf16 = 0; a.add = nullptr; a.ldadd = 0; a.add_kind = ADD_NONE;
         a.vec_ok = (d.N % 4 == 0) && ((uintptr_t)ws % 16 == 0);
@@ -166,11 +267,11 @@ static int launch_tile(const LaunchDesc& d, int variant, void* ws, hipStream_t s
     if (nwg <= 0) return SG_OK;
     if (nwg > 0x7FFFFFFF) return fail(SG_EINVAL, "launch grid too large");
     dim3 grid((unsigned)nwg, 1, (unsigned)S), block(256);
-    hipEvent_t stop1 = (S > 1) ? nullptr : d.ev_stop;
+    hipEvent_t stop1 = (S > 1) ? d.ev_mid : d.ev_stop;
     if (aligned)
-        hipExtLaunchKernelGGL((sg_gemm_tile_dma<BM, BN>), grid, block, 0, stream, d.ev_start, stop1, 0, a);
+        hipExtLaunchKernelGGL((sg_gemm_tile_dma<BM, BN>), grid, block, 0, stream, start, stop1, 0, a);
     else
-        hipExtLaunchKernelGGL((sg_gemm_tile<BM, BN>), grid, block, 0, stream, d.ev_start, stop1, 0, a);
+        hipExtLaunchKernelGGL((sg_gemm_tile<BM, BN>), grid, block, 0, stream, start, stop1, 0, a);
     SG_HIP(hipGetLastError());
     if (S > 1) {
         const int64_t total = d.M * d.N;
@@ -198,7 +299,7 @@ int launch_variant(int variant, const LaunchDesc& d, void* ws, hipStream_t strea
         return fail(SG_EINVAL, "dimension exceeds 2^31 - 1");
     if (d.Ml < d.M || d.Nl < d.N || d.Kl < d.K) return fail(SG_EINVAL, "launch dims below data dims");
     if (d.Kl <= 0) return fail(SG_EINVAL, "empty K extent");
-    if (launch_workspace_bytes(variant, d) > 0 && ws == nullptr)
+    if (packing_of(variant, d).part_bytes > 0 && ws == nullptr)
         return fail(SG_EINVAL, "split-K launch without workspace");
     switch (variant_tile(variant)) {
         case 0: return launch_tile<256, 256>(d, variant, ws, stream);

@@ -173,6 +173,8 @@ size_t plan_workspace(const Problem& pr, const std::vector<Leaf>& leaves, size_t
         if (!(L.first && L.last)) ksplit = true;
         LaunchDesc d{};
         d.M = L.m; d.N = L.n; d.K = L.k; d.Ml = L.Ml; d.Nl = L.Nl; d.Kl = L.Kl;
+        d.A = pr.A + L.m0 * pr.lda + L.k0; d.lda = pr.lda;   // operand views, as run_leaf
+        d.B = pr.B + L.k0 * pr.ldb + L.n0; d.ldb = pr.ldb;
         part = std::max(part, launch_workspace_bytes(L.variant, d));
     }
     size_t acc = (ksplit && pr.c_bf16) ? (size_t)pr.M * (size_t)pr.N * sizeof(float) : 0;
@@ -184,9 +186,10 @@ size_t plan_workspace(const Problem& pr, const std::vector<Leaf>& leaves, size_t
 // Enqueue one leaf.  Output routing (C FP32: accumulate in place; C BF16 with a K split:
 // accumulate in the FP32 plan accumulator W and round once in the last piece).
 int run_leaf(const Problem& pr, const Leaf& L, void* ws, size_t acc_bytes, hipStream_t s,
-             hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr) {
+             hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr, hipEvent_t ev_mid = nullptr) {
     LaunchDesc d{};
     d.ev_start = ev_start;
+    d.ev_mid = ev_mid;
     d.ev_stop = ev_stop;
     d.M = L.m; d.N = L.n; d.K = L.k; d.Ml = L.Ml; d.Nl = L.Nl; d.Kl = L.Kl;
     d.A = pr.A + L.m0 * pr.lda + L.k0; d.lda = pr.lda;
@@ -471,7 +474,8 @@ static int ensure_events(sg_ctx* ctx, size_t n) {
 // Time `reps` runs of the plan `leaves` (after one untimed run).  Every kernel launch carries
 // start/stop events stamped by its own dispatch packet, so a run's time is the sum of its
 // kernels' execution times (host launch gaps excluded).  Returns mean seconds per run; adds
-// per-variant kernel time, launch counts and algorithmic FLOP to the context's accounting.
+// per-variant tile-kernel time (a split-K reduction excluded: a third event ends at the tile
+// kernel), launch counts and algorithmic FLOP to the context's accounting.
 int time_plan(sg_ctx* ctx, const Problem& pr, const std::vector<Leaf>& leaves, int reps,
               hipStream_t s, double* sec, bool account) {
     size_t acc_bytes = 0;
@@ -482,28 +486,33 @@ int time_plan(sg_ctx* ctx, const Problem& pr, const std::vector<Leaf>& leaves, i
         if (rc) return rc;
     }
     const size_t nl = leaves.size();
-    const size_t ne = 2 * (size_t)reps * nl;
+    const size_t ne = 3 * (size_t)reps * nl;       // start, stop, end of the tile kernel
     rc = ensure_events(ctx, ne);
     if (rc) return rc;
     size_t e = 0;
     for (int r = 0; r < reps; ++r)
         for (const Leaf& L : leaves) {
-            rc = run_leaf(pr, L, ctx->ws, acc_bytes, s, ctx->events[e], ctx->events[e + 1]);
+            const bool split = variant_splits(L.variant) > 1;
+            rc = run_leaf(pr, L, ctx->ws, acc_bytes, s, ctx->events[e], ctx->events[e + 1],
+                          split ? ctx->events[e + 2] : nullptr);
             if (rc) return rc;
-            e += 2;
+            e += 3;
         }
-    SG_HIP(hipEventSynchronize(ctx->events[ne - 1]));
+    SG_HIP(hipEventSynchronize(ctx->events[ne - 2]));
     double total = 0.0;
     e = 0;
     for (int r = 0; r < reps; ++r)
         for (const Leaf& L : leaves) {
-            float ms = 0.f;
+            const bool split = variant_splits(L.variant) > 1;
+            float ms = 0.f, ms_kernel = 0.f;
             SG_HIP(hipEventElapsedTime(&ms, ctx->events[e], ctx->events[e + 1]));
-            e += 2;
+            if (split) SG_HIP(hipEventElapsedTime(&ms_kernel, ctx->events[e], ctx->events[e + 2]));
+            else ms_kernel = ms;
+            e += 3;
             total += (double)ms * 1e-3;
             if (account) {
                 ctx->acct_launches[L.variant] += 1;
-                ctx->acct_seconds[L.variant] += (double)ms * 1e-3;
+                ctx->acct_seconds[L.variant] += (double)ms_kernel * 1e-3;
                 ctx->acct_flops[L.variant] += 2.0 * (double)L.m * (double)L.n * (double)L.k;
             }
         }

@@ -33,9 +33,10 @@ struct LaunchDesc {
     int out_bf16;                  // 1: C is BF16, 0: FP32
     const void* add; int64_t ldadd;
     int add_kind;                  // 0 none, 1 FP32 addend, 2 BF16 addend (may alias C)
-    // optional timing events stamped by the dispatch itself (start of the first kernel of the
-    // launch, end of its last kernel); nullptr = no timing
-    hipEvent_t ev_start = nullptr, ev_stop = nullptr;
+    // Timing events stamped by the dispatch packets (may be null): ev_start at the start of the
+    // tile kernel, ev_mid at its end when a split-K reduction follows, ev_stop at the end of
+    // the launch's last kernel.
+    hipEvent_t ev_start = nullptr, ev_mid = nullptr, ev_stop = nullptr;
 };
 
 enum { ADD_NONE = 0, ADD_F32 = 1, ADD_BF16 = 2 };
@@ -53,9 +54,12 @@ inline int variant_splits(int v) { return 1 << (v % kSplitLevels); }
 
 // Number of non-empty K splits and the K extent of each for a launch of K extent Kl.
 void split_geometry(int variant, int64_t Kl, int* splits, int64_t* k_chunk);
-// Workspace bytes the variant needs for this launch (0 when it writes C directly).
+// Workspace bytes the variant needs for this launch: split-K partials, plus zero-padded copies
+// of operands the direct-to-LDS kernel cannot read in place (0 when neither applies).
 size_t launch_workspace_bytes(int variant, const LaunchDesc& d);
-// Enqueue one launch (and, for S > 1, its reduction).  ws must hold launch_workspace_bytes.
+// Enqueue one launch (operand copies if any, the tile kernel, and for S > 1 its reduction).
+// ws must hold launch_workspace_bytes, or be null: then a split-K launch fails and operands
+// that need a copy are read by the element-wise body instead.
 int launch_variant(int variant, const LaunchDesc& d, void* ws, hipStream_t stream);
 int lds_bytes_of_tile(int tile);
 

@@ -141,6 +141,34 @@ def test_leading_dimensions_views(ctx):
         assert np.all(out[M:, :] == -7.0) and np.all(out[:, N:] == -7.0)
 
 
+@pytest.mark.parametrize("variant", [0, 4, 8, 12, 13, 16, 20, 24, 27])
+@pytest.mark.parametrize("case", ["a_only", "b_only", "both", "a_base", "b_ld"])
+def test_packed_operands_integer_exact(ctx, variant, case):
+    """Operands the direct-to-LDS kernel cannot read in place are copied zero-padded first;
+    every combination (A only, B only, both, a misaligned base, a leading dimension that is
+    not a multiple of 8) must stay exact on integer inputs, over several tiles and a ragged
+    tail."""
+    import torch
+    M, N, K = {"a_only": (520, 392, 709), "b_only": (520, 389, 712), "both": (264, 331, 1003),
+               "a_base": (300, 264, 520), "b_ld": (300, 264, 520)}[case]
+    say("variant", variant, "case", case, M, N, K)
+    A, B = inputs(90 + variant, M, N, K, "int")
+    C = torch.full((M, N), float("nan"), dtype=torch.float32, device="cuda")
+    if case == "a_base":      # A starts one element past a 16-byte boundary
+        buf = torch.zeros(M * K + 8, dtype=torch.bfloat16, device="cuda")
+        buf[1:1 + M * K] = sg.to_device_bf16(A).reshape(-1)
+        dA, dB, lda, ldb = buf[1:1 + M * K].view(M, K), sg.to_device_bf16(B), K, N
+    elif case == "b_ld":      # B rows 3 elements apart beyond N
+        Bp = np.zeros((K, N + 3), dtype=B.dtype)
+        Bp[:, :N] = B
+        dA, dB, lda, ldb = sg.to_device_bf16(A), sg.to_device_bf16(Bp), K, N + 3
+    else:
+        dA, dB, lda, ldb = sg.to_device_bf16(A), sg.to_device_bf16(B), K, N
+    ctx.gemm(dA, dB, C, M=M, N=N, K=K, lda=lda, ldb=ldb, mode=sg.MODE_VARIANT, variant=variant)
+    torch.cuda.synchronize()
+    check_exact(C.cpu().numpy().astype(np.float64), A, B, F32)
+
+
 def test_errors_are_reported(ctx):
     import torch
     A = torch.zeros(8, 8, dtype=torch.bfloat16, device="cuda")
