@@ -322,7 +322,8 @@ def main():
     if args.workload == "grouped":
         if args.table:
             ctx.set_table(sg.Table.load(args.table))
-        res = run_grouped(args, sg, torch, ctx, stream)
+        # a stream of its own: graph capture needs a non-null stream (default priority)
+        res = run_grouped(args, sg, torch, ctx, torch.cuda.Stream())
         print(json.dumps(dict(
             metric="grouped BF16 GEMM throughput (hipGraph of persistent grouped launches)",
             value=res["graph_tflops"], unit="TFLOP/s", higher_is_better=True,
