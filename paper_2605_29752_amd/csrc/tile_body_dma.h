@@ -2,16 +2,17 @@
 //
 // The same tile as tile_body.h (256 threads, 2 x 2 waves, MFMA 16x16x32 BF16, B^T as the
 // first MFMA operand, LDS-staged epilogue), but the operands travel HBM -> LDS with
-// `buffer_load_dwordx4 ... lds`: no staging registers, so the loads of several K steps can be
-// in flight at once in a ring of LDS stages (32-deep K steps; four stages, two for 256 x 128).
+// `buffer_load_dwordx4 ... lds`: no staging registers, so the loads of later K stages are in
+// flight while a stage is multiplied, in a ring of LDS stages.  Stage depth BKD (32 or 64 of K,
+// one or two MFMA K steps) and ring depth are chosen per tile (DmaTile).
 //
 // LDS layout per stage (no padding: one DMA instruction writes 1 KiB contiguously):
-//  * A: BM rows x 32 BF16 (64 B), the four 16-byte chunks of row r stored at slot
-//    chunk ^ ((r >> 1) & 3).  A 16-byte-per-lane LDS read is served eight lanes (128 bytes, the
-//    32 four-byte banks) at a time; the eight rows those lanes read from fall in distinct
-//    (row parity, slot) pairs, so no two share a bank (measured: no bank-conflict cycles,
-//    where the (r >> 2) & 3 variant had one conflict cycle per access cycle);
-//  * B: 32 rows (K) x BN BF16 (N contiguous, as in HBM), the 16-byte chunk c of row k stored
+//  * A: BM rows x BKD BF16 (2 BKD bytes), 16-byte chunk c of row r stored at slot c ^ swz(r):
+//    swz(r) = (r >> 1) & 3 for 64-byte rows, r & 7 for 128-byte rows.  A 16-byte-per-lane LDS
+//    read is served eight lanes (128 bytes, the 32 four-byte banks) at a time; the eight rows
+//    those lanes read from land in distinct banks (measured: no bank-conflict cycles, where
+//    (r >> 2) & 3 on 64-byte rows had one conflict cycle per access cycle);
+//  * B: BKD rows (K) x BN BF16 (N contiguous, as in HBM), the 16-byte chunk c of row k stored
 //    at slot c ^ swz(k), swz(k) = (2 (k & 3)) ^ (8 ((k >> 3) & 3)) (within the row's chunks).
 //    A B fragment (8 consecutive K at one N per lane) comes from two ds_read_b64_tr_b16: within
 //    each 16-lane group, result[i][e] is element i % 4 of the 4 elements at the address given by
@@ -27,13 +28,20 @@ namespace sg {
 
 template <int BM, int BN>
 struct DmaTile {
-    static constexpr int BKD = 32;                       // K per stage
-    // Ring depth.  The 256 x 128 tiles take two stages: their 48 KiB ring lets two work-groups
-    // share a CU, which hides more latency than deeper prefetch in one work-group (4096^3:
-    // 1,070-1,140 against 730 TFLOP/s with four stages).  The other tiles keep four: 256 x 256
-    // runs one work-group per CU either way, and the smaller tiles measure faster on
-    // mid-sized shapes with deeper prefetch.
-    static constexpr int STAGES = (BM * BN == 256 * 128) ? 2 : 4;
+    // Stage depth and ring depth per tile, from measurements (4096^3, TFLOP/s):
+    //  * tiles up to 128 x 128: 64-deep stages (two MFMA K steps per barrier) in a two-stage ring;
+    //    the per-step cost of waits, barrier and load issue is paid once per 64 of K
+    //    (128 x 128: 912 -> 1,085; 64 x 64: 578 -> 738; 2048^3 gains 13-26 %);
+    //  * 256 x 128 / 128 x 256: 32-deep stages, two-stage ring: 48 KiB lets two work-groups share
+    //    a CU, which hides more latency than deeper prefetch in one (1,070-1,140 against 730
+    //    with four stages; 64-deep stages would take 96 KiB and one work-group: 818);
+    //  * 256 x 256: 32-deep stages, four-stage ring (one work-group per CU either way).
+    static constexpr bool SMALL = BM * BN <= 128 * 128;
+    static constexpr int BKD = SMALL ? 64 : 32;          // K per stage
+    static constexpr int SUB = BKD / 32;                 // MFMA K steps per stage
+    static constexpr int A_CH = BKD / 8;                 // 16-byte chunks per A row
+    static constexpr int A_ROWS_PER_INSTR = 512 / BKD;   // 1 KiB = 512 BF16
+    static constexpr int STAGES = (BM == 256 && BN == 256) ? 4 : 2;
     static constexpr int A_BYTES = BM * BKD * 2;
     static constexpr int B_BYTES = BKD * BN * 2;
     static constexpr int STAGE_BYTES = A_BYTES + B_BYTES;
@@ -126,12 +134,12 @@ __device__ __forceinline__ void tile_body_dma(const KArgs& p, const int m0, cons
     // Per-lane DMA geometry (fixed over the loop).
     // A instruction i of this wave covers tile rows 16 q .. 16 q + 15, q = wave * A_INSTR + i;
     // lane -> row 16 q + lane / 4, slot lane % 4, which holds chunk slot ^ a_swz(row).
-    const int a_row0 = lane >> 2;
-    const int a_slot = lane & 3;
+    const int a_row0 = lane / T::A_CH;
+    const int a_slot = lane % T::A_CH;
     // B instruction i covers K rows q * R .. q * R + R - 1, q = wave * B_INSTR + i.
     const int b_row0 = lane / T::B_CHUNKS;
     const int b_slot = lane % T::B_CHUNKS;
-    auto a_swz = [](int row) { return (row >> 1) & 3; };
+    auto a_swz = [](int row) { return T::BKD == 32 ? (row >> 1) & 3 : row & 7; };
     auto b_swz = [](int k) { return ((2 * (k & 3)) ^ (8 * ((k >> 3) & 3))) & (T::B_CHUNKS - 1); };
 
     typedef __attribute__((address_space(3))) char lds_char;
@@ -143,7 +151,7 @@ __device__ __forceinline__ void tile_body_dma(const KArgs& p, const int m0, cons
     uint32_t a_off[T::A_INSTR], b_off[T::B_INSTR];
 #pragma unroll
     for (int i = 0; i < T::A_INSTR; ++i) {
-        const int row = (wave_u * T::A_INSTR + i) * 16 + a_row0;
+        const int row = (wave_u * T::A_INSTR + i) * T::A_ROWS_PER_INSTR + a_row0;
         const int chunk = a_slot ^ a_swz(row);
         a_off[i] = (m0 + row < p.M) ? (uint32_t)(((int64_t)(m0 + row) * p.lda + kb + chunk * 8) * 2) : kOut;
     }
@@ -166,7 +174,7 @@ __device__ __forceinline__ void tile_body_dma(const KArgs& p, const int m0, cons
             const int q = wave_u * T::A_INSTR + d;
             uint32_t o = a_off[d] + (uint32_t)kt * a_step;
             if (!interior) {
-                const int chunk = a_slot ^ a_swz(q * 16 + a_row0);
+                const int chunk = a_slot ^ a_swz(q * T::A_ROWS_PER_INSTR + a_row0);
                 if (k0 + chunk * 8 >= p.K) o = kOut;
             }
             asm volatile("" : "+v"(o));
@@ -200,53 +208,51 @@ __device__ __forceinline__ void tile_body_dma(const KArgs& p, const int m0, cons
     // TFLOP/s); the other tiles issue them in one burst before the MFMAs, which measures
     // faster for them (the two-stage 256 x 128 ring needs its loads out as early as possible,
     // and the smaller tiles' rows are too short to cover a load's issue).
-    auto compute = [&](int slot, bool issue_next, int kt_next, int slot_next, bool burst = false) {
+    auto compute = [&](int slot, bool issue_next, int kt_next, int slot_next) {
         const char* stage = (const char*)smem + slot * T::STAGE_BYTES;
-        bf16x8_t af[FM], bfr[FN];
 #pragma unroll
-        for (int i = 0; i < FM; ++i) {
-            const int row = wm * WM + i * 16 + lr;
-            af[i] = *(const bf16x8_t*)(stage + row * 64 + ((lg ^ a_swz(row)) << 4));
-        }
-        const int tk = lg * 8 + (lr >> 2);               // K row this lane points at (+4: second read)
+        for (int h = 0; h < T::SUB; ++h) {
+            bf16x8_t af[FM], bfr[FN];
 #pragma unroll
-        for (int j = 0; j < FN; ++j) {
-            const int n = wn * WN + j * 16 + 4 * (lr & 3);  // first of 4 columns this lane points at
-            bf16x4_t h[2];
-#pragma unroll
-            for (int r = 0; r < 2; ++r) {
-                const int k = tk + 4 * r;
-                const int off = T::A_BYTES + k * BN * 2 + (((n >> 3) ^ b_swz(k)) << 4) + (n & 7) * 2;
-                h[r] = __builtin_amdgcn_ds_read_tr16_b64_v4bf16(
-                    (lds_bf16x4*)((lds_char*)lds + slot * T::STAGE_BYTES + off));
+            for (int i = 0; i < FM; ++i) {
+                const int row = wm * WM + i * 16 + lr;
+                af[i] = *(const bf16x8_t*)(stage + row * (T::BKD * 2) + (((4 * h + lg) ^ a_swz(row)) << 4));
             }
-            bfr[j] = bf16x8_t{h[0][0], h[0][1], h[0][2], h[0][3], h[1][0], h[1][1], h[1][2], h[1][3]};
-        }
-        // With `burst`, the next stage's loads go out while the fragment reads are in flight:
-        // the LDS read latency hides behind the load issue instead of adding to it (the loads
-        // write the slot of an earlier step, not the one being read).  Four-stage rings
-        // (64 x 128 at 2048^3: 540 -> 610 TFLOP/s; 64 x 64 at 1024 x 1024 x 4096: 267 -> 290).
-        if (burst) issue(kt_next, slot_next);
-        // raised wave priority while the MFMAs issue, so that the waves of a CU that are
-        // ready to multiply are preferred over those issuing loads
-        __builtin_amdgcn_s_setprio(1);
+            const int tk = 32 * h + lg * 8 + (lr >> 2);  // K row this lane points at (+4: second read)
 #pragma unroll
-        for (int i = 0; i < FM; ++i) {
+            for (int j = 0; j < FN; ++j) {
+                const int n = wn * WN + j * 16 + 4 * (lr & 3);  // first of 4 columns this lane points at
+                bf16x4_t hv[2];
 #pragma unroll
-            for (int j = 0; j < FN; ++j)
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bfr[j], af[i], acc[i][j], 0, 0, 0);
-            if constexpr (SPREAD) {
-                // loads ((i+1) PER_STAGE / FM) - (i PER_STAGE / FM) follow MFMA row i
-                __builtin_amdgcn_sched_barrier(0);
-                if (issue_next) {
-#pragma unroll
-                    for (int d = i * PER_STAGE / FM; d < (i + 1) * PER_STAGE / FM; ++d)
-                        issue_one(kt_next, slot_next, d);
+                for (int r = 0; r < 2; ++r) {
+                    const int k = tk + 4 * r;
+                    const int off = T::A_BYTES + k * BN * 2 + (((n >> 3) ^ b_swz(k)) << 4) + (n & 7) * 2;
+                    hv[r] = __builtin_amdgcn_ds_read_tr16_b64_v4bf16(
+                        (lds_bf16x4*)((lds_char*)lds + slot * T::STAGE_BYTES + off));
                 }
-                __builtin_amdgcn_sched_barrier(0);
+                bfr[j] = bf16x8_t{hv[0][0], hv[0][1], hv[0][2], hv[0][3], hv[1][0], hv[1][1], hv[1][2], hv[1][3]};
             }
+            // raised wave priority while the MFMAs issue, so that the waves of a CU that are
+            // ready to multiply are preferred over those issuing loads
+            __builtin_amdgcn_s_setprio(1);
+#pragma unroll
+            for (int i = 0; i < FM; ++i) {
+#pragma unroll
+                for (int j = 0; j < FN; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bfr[j], af[i], acc[i][j], 0, 0, 0);
+                if constexpr (SPREAD) {
+                    // loads ((i+1) PER_STAGE / FM) - (i PER_STAGE / FM) follow MFMA row i
+                    __builtin_amdgcn_sched_barrier(0);
+                    if (h == 0 && issue_next) {
+#pragma unroll
+                        for (int d = i * PER_STAGE / FM; d < (i + 1) * PER_STAGE / FM; ++d)
+                            issue_one(kt_next, slot_next, d);
+                    }
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+            }
+            __builtin_amdgcn_s_setprio(0);
         }
-        __builtin_amdgcn_s_setprio(0);
     };
 
     // Step kt waits until this wave's loads of step kt have landed (at most `later` later
@@ -285,14 +291,11 @@ __device__ __forceinline__ void tile_body_dma(const KArgs& p, const int m0, cons
         // loops get copied through a temporary before every MFMA by the compiler.
         for (int kt = 0; kt < nk; ++kt) {
             sync_step(min(nk - 1, kt + S - 2) - kt);
-            const bool more = kt + S - 1 < nk;
-            if constexpr (S == 2) {
-                // a one-step lookahead needs the loads out before anything else
-                if (more) issue(kt + S - 1, (kt + S - 1) % S);
-                compute(kt % S, false, 0, 0);
-            } else {
-                compute(kt % S, false, kt + S - 1, (kt + S - 1) % S, more);
-            }
+            // The two-stage ring's one-step lookahead needs the loads out before anything else
+            // (issuing them after the fragment reads, which hides the LDS read latency, measured
+            // slower for these tiles; it helped only four-stage rings of 32-deep stages).
+            if (kt + S - 1 < nk) issue(kt + S - 1, (kt + S - 1) % S);
+            compute(kt % S, false, 0, 0);
         }
     }
     __syncthreads();                            // ring no longer read: the epilogue reuses it
