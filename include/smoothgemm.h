@@ -101,7 +101,7 @@ typedef struct sg_variant_info {
 int sg_num_variants(void);
 int sg_variant_info_get(int variant, sg_variant_info* out);
 
-/* ---- landscape metrics (paper Sec. 2.4, Sec. 8.6) -------------------------------------------
+/* ---- landscape metrics (paper Sec. 2 definitions, Sec. 8.5 Table 17) -------------------------------------------
  * sg_roughness: sum_i |T[i+1] - T[i]| / (n - 1); n < 2 returns NaN.
  * sg_landscape_stats: tflops is an nM x nN x nK array (K fastest) of throughputs; fills
  * mean, peak, roughness along M, N and K (each averaged over every line along that axis) and
@@ -112,7 +112,7 @@ typedef struct sg_stats {
 } sg_stats;
 int sg_landscape_stats(const double* tflops, int nM, int nN, int nK, sg_stats* out);
 
-/* ---- sweep driver (paper Sec. 3 timing protocol, Sec. 4.5 randomized order) -----------------
+/* ---- sweep driver (paper Sec. 3 timing protocol, Sec. 5.4 randomized order) -----------------
  * Runs the n shapes in the order given (shuffle them for the randomized protocol) with
  * `warmup` untimed runs of the first shape up front, then per shape one untimed run and `reps`
  * timed runs; out_sec[i] = mean seconds of one run of shape i.  Each run is one complete

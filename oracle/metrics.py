@@ -1,7 +1,8 @@
 """Landscape metrics -- oracle, test infrastructure only.
 
-Definitions of the paper's Sec. 2.4 (measurement definitions) and Sec. 8.6 (3-D aggregate),
-plus the ideal compute landscape of Sec. 9.1.
+Definitions of the paper's Sec. 2 (its closing measurement definitions) and Sec. 8.5, Table 17 (3-D aggregate),
+the ideal compute landscape and the first-principles optimal of Sec. 9, and the attainment /
+roughness-ratio grading of Sec. 10 (Kernel Optimality Levels).
 """
 from __future__ import annotations
 
@@ -57,3 +58,58 @@ def ideal_tflops(M: int, N: int, peak: float, cores: int, tile: int) -> float:
 def tile_utilisation(N: int, tile: int) -> float:
     """Fraction of launched tile columns that hold data: N / (ceil(N/T) T)."""
     return N / (math.ceil(N / tile) * tile)
+
+
+def wave_efficiency(M: int, N: int, tile: int, cores: int) -> float:
+    """Sec. 9.2, compute term: W = ceil(M/T) ceil(N/T) work-groups run in ceil(W/C) waves of C
+    cores, so a fraction W / (ceil(W/C) C) of the launched core-slots does work."""
+    W = math.ceil(M / tile) * math.ceil(N / tile)
+    return W / (math.ceil(W / cores) * cores)
+
+
+def optimal_tflops(M: int, N: int, K: int, peak: float, cores: int, bw_gbs: float,
+                   tiles=(256, 128, 64), c_bytes: int = 2) -> float:
+    """Sec. 9.2: t_opt = min over tiles T of max(t_compute(T), t_memory), with
+    t_compute(T) = 2MNK / (peak wave_efficiency(T)) and t_memory = (2MK + 2KN + c_bytes MN) / BW
+    (the channel-utilisation factors taken as 1: this HBM's address hash is not public).
+    Returns 2MNK / t_opt in TFLOP/s (peak in TFLOP/s, BW in GB/s)."""
+    flop = 2.0 * M * N * K
+    t_mem = (2.0 * M * K + 2.0 * K * N + float(c_bytes) * M * N) / (bw_gbs * 1e9)
+    best = math.inf
+    for T in tiles:
+        t_comp = flop / (peak * 1e12 * wave_efficiency(M, N, T, cores))
+        best = min(best, max(t_comp, t_mem))
+    return flop / best / 1e12
+
+
+# Sec. 10, Table 19: throughput bands by attainment tau, smoothness bands by roughness ratio rho.
+def throughput_band(tau: float) -> int:
+    if tau >= 0.95:
+        return 3
+    if tau >= 0.75:
+        return 2
+    if tau >= 0.50:
+        return 1
+    return 0
+
+
+def smoothness_band(rho: float) -> int:
+    if rho <= 1.25:
+        return 3
+    if rho <= 2.0:
+        return 2
+    if rho <= 3.0:
+        return 1
+    return 0
+
+
+def kol_grade(actual: np.ndarray, optimal: np.ndarray):
+    """Sec. 10.2-10.3 over a landscape (M x N or M x N x K array, N on axis 1):
+    tau = mean(A) / mean(O); rho = R(A) / R(O) with R the N-axis roughness averaged over all
+    lines; level = min(throughput band, smoothness band)."""
+    A = np.asarray(actual, dtype=np.float64)
+    O = np.asarray(optimal, dtype=np.float64)
+    tau = float(A.mean() / O.mean())
+    rho = float(roughness_along(A, 1) / roughness_along(O, 1))
+    t, s_ = throughput_band(tau), smoothness_band(rho)
+    return {"tau": tau, "rho": rho, "t_band": t, "s_band": s_, "level": min(t, s_)}
