@@ -57,6 +57,27 @@ def stack_stats(sg, sec, sizes):
             "frac_of_peak_mean": st["mean"] / PEAK_BF16_TFLOPS}
 
 
+def first_principles(sg, stack_secs, sizes, step, n):
+    """The grid's ideal ceiling and first-principles optimal (paper Sec. 9: MI355X datasheet
+    integers, tiles {256, 128, 64}, BF16 output) and each stack's Kernel Optimality Level against
+    the optimal (Sec. 10), on the K = max slice (the paper's grading) and over the whole grid."""
+    M = sizes[:, None, None]
+    N = sizes[None, :, None]
+    K = sizes[None, None, :]
+    ideal = sg.ideal_landscape(step, n, n, n, tile=256)
+    opt = sg.optimal_landscape(step, n, n, n, tiles=(256, 128, 64), c_bytes=2)
+    out = {"hw": sg.MI355X, "tiles": [256, 128, 64],
+           "ideal": {k: v for k, v in sg.landscape_stats(ideal).items() if k in ("mean", "roughness_n", "roughness_3d")},
+           "optimal": {k: v for k, v in sg.landscape_stats(opt).items() if k in ("mean", "roughness_n", "roughness_3d")},
+           "kol": {}}
+    out["ideal"]["slice_mean"] = float(ideal[:, :, -1].mean())
+    out["optimal"]["slice_mean"] = float(opt[:, :, -1].mean())
+    for name, sec in stack_secs.items():
+        tf = 2.0 * M * N * K / (sec * 1e12)
+        out["kol"][name] = {"slice": sg.kol_grade(tf[:, :, -1], opt[:, :, -1]), "grid": sg.kol_grade(tf, opt)}
+    return out
+
+
 def kernel_source_hash() -> str:
     import hashlib
     h = hashlib.sha1()
@@ -411,13 +432,14 @@ def main():
     exec_sec[cells] = np.mean(passes, axis=0)
     exec_sec = exec_sec.reshape(n, n, n)
 
-    stacks = {
-        "plain_%s" % sg.variant_info(args.plain_variant).name: stack_stats(sg, T0all[plain_row], sizes),
-        "best_of_%d" % len(variants): stack_stats(sg, T0best, sizes),
-        "dp_pad_table": stack_stats(sg, T1, sizes),
-        "dp_split_pad_table": stack_stats(sg, T2, sizes),
-        "dp_split_pad_executed": stack_stats(sg, exec_sec, sizes),
+    stack_secs = {
+        "plain_%s" % sg.variant_info(args.plain_variant).name: T0all[plain_row],
+        "best_of_%d" % len(variants): T0best,
+        "dp_pad_table": T1,
+        "dp_split_pad_table": T2,
+        "dp_split_pad_executed": exec_sec,
     }
+    stacks = {name: stack_stats(sg, sec, sizes) for name, sec in stack_secs.items()}
     # best single variant by mean over the sweep
     means = [stack_stats(sg, T0all[r], sizes)["mean_tflops"] for r in range(len(variants))]
     best_single = variants[int(np.argmax(means))]
@@ -478,6 +500,7 @@ def main():
                           "roughness_slice": ex["slice_k%d_roughness_n" % maxdim] /
                           plain["slice_k%d_roughness_n" % maxdim] - 1.0},
         "stacks": stacks,
+        "first_principles": first_principles(sg, stack_secs, sizes, args.step, n),
         "dp_actions": {names[a]: c / n ** 3 for a, c in sorted(actions.items())},
         "table_build_s": table_s,
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_BF16_TFLOPS,

@@ -112,6 +112,29 @@ typedef struct sg_stats {
 } sg_stats;
 int sg_landscape_stats(const double* tflops, int nM, int nN, int nK, sg_stats* out);
 
+/* ---- first-principles landscape and Kernel Optimality Levels (paper Sec. 9, Sec. 10) --------
+ * Computed from datasheet integers alone, no kernel run.  hw: peak (TFLOP/s, dense), cores (the
+ * work-group slots of one wave: compute units), bandwidth (GB/s).  Landscapes are over the grid
+ * cells (M, N, K) = ((i+1) step, (j+1) step, (k+1) step), written as an n_m x n_n x n_k array,
+ * K fastest (the layout of sg_landscape_stats).
+ * sg_ideal_landscape (Sec. 9.1): peak * min(1, W / C), W = ceil(M/T) ceil(N/T) for the tile T.
+ * sg_optimal_landscape (Sec. 9.2): 2MNK / t_opt, t_opt = min over the ntiles square tile edges T
+ *   of max(2MNK / (peak * eta(T)), t_mem), eta(T) = W_T / (ceil(W_T / C) C) the fraction of the
+ *   launched core-slots that work (wave quantization), t_mem = (2MK + 2KN + c_bytes MN) / BW
+ *   (per-channel utilisation taken as 1: the HBM address hash is not public).
+ * sg_kol_grade (Sec. 10.2-10.3): attainment tau = mean(actual) / mean(optimal); roughness ratio
+ *   rho = R(actual) / R(optimal), R the N-axis roughness averaged over every line along N;
+ *   bands of Table 19 (tau: < 0.5, < 0.75, < 0.95, else; rho: > 3, > 2, > 1.25, else) and level
+ *   = min(t_band, s_band), 0 (L0) to 3 (L3).  Arrays are n_m x n_n x n_k (K fastest), n_n >= 2.
+ * NULL pointers, non-positive sizes or hardware values give SG_EINVAL. */
+typedef struct sg_hw { double peak_tflops; int cores; double bw_gbs; } sg_hw;
+typedef struct sg_kol { double tau, rho; int t_band, s_band, level; } sg_kol;
+struct sg_grid;
+int sg_ideal_landscape(const struct sg_grid* grid, const sg_hw* hw, int tile, double* out);
+int sg_optimal_landscape(const struct sg_grid* grid, const sg_hw* hw, const int* tiles, int ntiles,
+                         int c_bytes, double* out);
+int sg_kol_grade(const double* actual, const double* optimal, int n_m, int n_n, int n_k, sg_kol* out);
+
 /* ---- sweep driver (paper Sec. 3 timing protocol, Sec. 5.4 randomized order) -----------------
  * Runs the n shapes in the order given (shuffle them for the randomized protocol) with
  * `warmup` untimed runs of the first shape up front, then per shape one untimed run and `reps`

@@ -58,6 +58,14 @@ class sg_grid(ctypes.Structure):
     _fields_ = [("step", _i32), ("n_m", _i32), ("n_n", _i32), ("n_k", _i32)]
 
 
+class sg_hw(ctypes.Structure):
+    _fields_ = [("peak_tflops", _d), ("cores", _i32), ("bw_gbs", _d)]
+
+
+class sg_kol(ctypes.Structure):
+    _fields_ = [("tau", _d), ("rho", _d), ("t_band", _i32), ("s_band", _i32), ("level", _i32)]
+
+
 class sg_plan_rec(ctypes.Structure):
     _fields_ = [("action", _i32), ("arg", _i32), ("variant", _i32), ("t0", _d), ("t1", _d), ("t2", _d)]
 
@@ -77,6 +85,9 @@ _SIGS = {
     "sg_variant_info_get": (_i32, [_i32, ctypes.POINTER(sg_variant_info)]),
     "sg_roughness": (_d, [_p, _i64]),
     "sg_landscape_stats": (_i32, [_p, _i32, _i32, _i32, ctypes.POINTER(sg_stats)]),
+    "sg_ideal_landscape": (_i32, [ctypes.POINTER(sg_grid), ctypes.POINTER(sg_hw), _i32, _p]),
+    "sg_optimal_landscape": (_i32, [ctypes.POINTER(sg_grid), ctypes.POINTER(sg_hw), _p, _i32, _i32, _p]),
+    "sg_kol_grade": (_i32, [_p, _p, _i32, _i32, _i32, ctypes.POINTER(sg_kol)]),
     "sg_sweep": (_i32, [_p, _p, _i64, _i32, _i32, _i32, _i32, _i32, _p, _p, _p, _p, _p]),
     "sg_sweep_kernel_times": (_i32, [_p, _p, _p, _p]),
     "sg_table_from_t0": (_i32, [ctypes.POINTER(sg_grid), _p, _p, _i32, ctypes.POINTER(_p)]),
@@ -238,6 +249,45 @@ def landscape_stats(tflops_mnk: np.ndarray) -> dict:
     check(lib().sg_landscape_stats(_arr(t), t.shape[0], t.shape[1], t.shape[2], ctypes.byref(st)))
     return {"mean": st.mean, "peak": st.peak, "roughness_m": st.rough_m, "roughness_n": st.rough_n,
             "roughness_k": st.rough_k, "roughness_3d": st.rough_3d}
+
+
+MI355X = {"peak_tflops": 2516.6, "cores": 256, "bw_gbs": 8000.0}   # dense BF16 MFMA, CUs, HBM3E
+
+
+def _hw(hw) -> "sg_hw":
+    return sg_hw(float(hw["peak_tflops"]), int(hw["cores"]), float(hw["bw_gbs"]))
+
+
+def ideal_landscape(step: int, n_m: int, n_n: int, n_k: int, tile: int = 256, hw=MI355X) -> np.ndarray:
+    """Ideal ceiling over the grid (paper Sec. 9.1), n_m x n_n x n_k TFLOP/s."""
+    out = np.zeros((n_m, n_n, n_k), dtype=np.float64)
+    g = sg_grid(step, n_m, n_n, n_k)
+    check(lib().sg_ideal_landscape(ctypes.byref(g), ctypes.byref(_hw(hw)), tile, _arr(out)))
+    return out
+
+
+def optimal_landscape(step: int, n_m: int, n_n: int, n_k: int, tiles=(256, 128, 64), c_bytes: int = 2,
+                      hw=MI355X) -> np.ndarray:
+    """First-principles optimal landscape over the grid (paper Sec. 9.2), TFLOP/s."""
+    out = np.zeros((n_m, n_n, n_k), dtype=np.float64)
+    g = sg_grid(step, n_m, n_n, n_k)
+    t = (ctypes.c_int * len(tiles))(*tiles)
+    check(lib().sg_optimal_landscape(ctypes.byref(g), ctypes.byref(_hw(hw)), t, len(tiles), c_bytes, _arr(out)))
+    return out
+
+
+def kol_grade(actual: np.ndarray, optimal: np.ndarray) -> dict:
+    """(tau, rho, bands, level) of a landscape against the optimal (paper Sec. 10)."""
+    a = np.ascontiguousarray(actual, dtype=np.float64)
+    o = np.ascontiguousarray(optimal, dtype=np.float64)
+    if a.shape != o.shape:
+        raise ValueError("landscapes differ in shape")
+    if a.ndim == 2:
+        a, o = a[:, :, None], o[:, :, None]
+    k = sg_kol()
+    check(lib().sg_kol_grade(_arr(np.ascontiguousarray(a)), _arr(np.ascontiguousarray(o)),
+                             a.shape[0], a.shape[1], a.shape[2], ctypes.byref(k)))
+    return {"tau": k.tau, "rho": k.rho, "t_band": k.t_band, "s_band": k.s_band, "level": k.level}
 
 
 class Table:

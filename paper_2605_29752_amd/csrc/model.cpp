@@ -1,0 +1,106 @@
+// First-principles GEMM landscape and Kernel Optimality Levels (paper Sec. 9 and Sec. 10): the
+// ideal ceiling, the optimal achievable landscape from datasheet integers (wave quantization
+// over the compute units, memory roofline), and the (tau, rho, level) grade of a measured
+// landscape against it.  Host code only.
+#include <algorithm>
+#include <cmath>
+#include <limits>
+
+#include "sg_internal.h"
+
+namespace {
+
+bool hw_ok(const sg_hw* hw) {
+    return hw && hw->peak_tflops > 0.0 && hw->cores > 0 && hw->bw_gbs > 0.0;
+}
+
+bool grid_ok(const sg_grid* g) {
+    return g && g->step > 0 && g->n_m > 0 && g->n_n > 0 && g->n_k > 0;
+}
+
+double ceil_div(double a, double b) { return std::ceil(a / b); }
+
+// Fraction of the launched core-slots that hold work: W / (ceil(W / C) C).
+double wave_efficiency(double M, double N, int tile, int cores) {
+    const double W = ceil_div(M, tile) * ceil_div(N, tile);
+    return W / (ceil_div(W, cores) * cores);
+}
+
+// Mean |difference| of consecutive entries along N, averaged over every line along N.
+double roughness_n(const double* T, int nm, int nn, int nk) {
+    double s = 0.0;
+    for (int m = 0; m < nm; ++m)
+        for (int k = 0; k < nk; ++k) {
+            double line = 0.0;
+            for (int n = 0; n + 1 < nn; ++n)
+                line += std::fabs(T[((int64_t)m * nn + n + 1) * nk + k] - T[((int64_t)m * nn + n) * nk + k]);
+            s += line / (nn - 1);
+        }
+    return s / ((double)nm * nk);
+}
+
+int throughput_band(double tau) { return tau >= 0.95 ? 3 : tau >= 0.75 ? 2 : tau >= 0.50 ? 1 : 0; }
+int smoothness_band(double rho) { return rho <= 1.25 ? 3 : rho <= 2.0 ? 2 : rho <= 3.0 ? 1 : 0; }
+
+}  // namespace
+
+extern "C" {
+
+int sg_ideal_landscape(const sg_grid* g, const sg_hw* hw, int tile, double* out) {
+    if (!grid_ok(g) || !hw_ok(hw) || tile <= 0 || !out) return sg::fail(SG_EINVAL, "sg_ideal_landscape: bad argument");
+    int64_t i = 0;
+    for (int a = 0; a < g->n_m; ++a)
+        for (int b = 0; b < g->n_n; ++b)
+            for (int c = 0; c < g->n_k; ++c) {
+                const double M = (double)(a + 1) * g->step, N = (double)(b + 1) * g->step;
+                const double W = ceil_div(M, tile) * ceil_div(N, tile);
+                out[i++] = hw->peak_tflops * std::min(1.0, W / hw->cores);
+            }
+    return SG_OK;
+}
+
+int sg_optimal_landscape(const sg_grid* g, const sg_hw* hw, const int* tiles, int ntiles, int c_bytes,
+                         double* out) {
+    if (!grid_ok(g) || !hw_ok(hw) || !tiles || ntiles <= 0 || c_bytes <= 0 || !out)
+        return sg::fail(SG_EINVAL, "sg_optimal_landscape: bad argument");
+    for (int t = 0; t < ntiles; ++t)
+        if (tiles[t] <= 0) return sg::fail(SG_EINVAL, "sg_optimal_landscape: tile edge must be positive");
+    const double peak = hw->peak_tflops * 1e12, bw = hw->bw_gbs * 1e9;
+    int64_t i = 0;
+    for (int a = 0; a < g->n_m; ++a)
+        for (int b = 0; b < g->n_n; ++b)
+            for (int c = 0; c < g->n_k; ++c) {
+                const double M = (double)(a + 1) * g->step, N = (double)(b + 1) * g->step;
+                const double K = (double)(c + 1) * g->step;
+                const double flop = 2.0 * M * N * K;
+                const double t_mem = (2.0 * M * K + 2.0 * K * N + (double)c_bytes * M * N) / bw;
+                double best = std::numeric_limits<double>::infinity();
+                for (int t = 0; t < ntiles; ++t) {
+                    const double t_comp = flop / (peak * wave_efficiency(M, N, tiles[t], hw->cores));
+                    best = std::min(best, std::max(t_comp, t_mem));
+                }
+                out[i++] = flop / best / 1e12;
+            }
+    return SG_OK;
+}
+
+int sg_kol_grade(const double* actual, const double* optimal, int nm, int nn, int nk, sg_kol* out) {
+    if (!actual || !optimal || !out || nm < 1 || nn < 2 || nk < 1)
+        return sg::fail(SG_EINVAL, "sg_kol_grade: bad argument (n_n must be >= 2)");
+    const int64_t total = (int64_t)nm * nn * nk;
+    double sa = 0.0, so = 0.0;
+    for (int64_t i = 0; i < total; ++i) {
+        sa += actual[i];
+        so += optimal[i];
+    }
+    const double ro = roughness_n(optimal, nm, nn, nk);
+    if (so <= 0.0 || ro <= 0.0) return sg::fail(SG_EINVAL, "sg_kol_grade: optimal landscape has no mean or no roughness");
+    out->tau = sa / so;
+    out->rho = roughness_n(actual, nm, nn, nk) / ro;
+    out->t_band = throughput_band(out->tau);
+    out->s_band = smoothness_band(out->rho);
+    out->level = std::min(out->t_band, out->s_band);
+    return SG_OK;
+}
+
+}  // extern "C"

@@ -135,6 +135,44 @@ def test_ideal_landscape_through_library():
     assert abs(st["mean"] - 97.2) <= 0.05 and abs(st["roughness_n"] - 2.0) <= 0.05
 
 
+def test_first_principles_landscapes_match_oracle():
+    step, nm, nn, nk = 128, 9, 11, 5
+    hw = {"peak_tflops": 2516.6, "cores": 256, "bw_gbs": 8000.0}
+    ideal = sg.ideal_landscape(step, nm, nn, nk, tile=256, hw=hw)
+    opt = sg.optimal_landscape(step, nm, nn, nk, tiles=(256, 128, 64), c_bytes=2, hw=hw)
+    for a in range(nm):
+        for b in range(nn):
+            for c in range(nk):
+                M, N, K = (a + 1) * step, (b + 1) * step, (c + 1) * step
+                assert ideal[a, b, c] == pytest.approx(om.ideal_tflops(M, N, 2516.6, 256, 256), rel=1e-12)
+                assert opt[a, b, c] == pytest.approx(
+                    om.optimal_tflops(M, N, K, 2516.6, 256, 8000.0, tiles=(256, 128, 64), c_bytes=2), rel=1e-12)
+    # the paper's own ideal through the library: Arc B580 constants (Sec. 9.1)
+    b580 = sg.ideal_landscape(128, 32, 32, 2, tile=256, hw={"peak_tflops": 108.2, "cores": 20, "bw_gbs": 451.0})
+    st = sg.landscape_stats(b580)
+    assert abs(st["mean"] - 97.2) <= 0.05 and abs(st["roughness_n"] - 2.0) <= 0.05
+    with pytest.raises(sg.SGError):
+        sg.optimal_landscape(128, 2, 2, 2, tiles=(0,), hw=hw)
+    with pytest.raises(sg.SGError):
+        sg.ideal_landscape(128, 2, 2, 2, hw={"peak_tflops": 0.0, "cores": 256, "bw_gbs": 1.0})
+
+
+def test_kol_grade_matches_oracle():
+    rng = np.random.default_rng(5)
+    O = rng.uniform(500, 2500, size=(6, 7, 4))
+    for A in (O, 0.3 * O, O + rng.uniform(-200, 200, size=O.shape), np.sort(O, axis=1)):
+        got = sg.kol_grade(A, O)
+        want = om.kol_grade(A, O)
+        for k in ("tau", "rho"):
+            assert got[k] == pytest.approx(want[k], rel=1e-12)
+        for k in ("t_band", "s_band", "level"):
+            assert got[k] == want[k]
+    g2 = sg.kol_grade(O[:, :, 0], O[:, :, 0])          # a 2-D slice
+    assert g2["level"] == 3
+    with pytest.raises(sg.SGError):
+        sg.kol_grade(np.ones((2, 1, 1)), np.ones((2, 1, 1)))
+
+
 def test_synthetic_plans_cover_every_action():
     """The GPU plan-execution tests rely on these synthetic tables producing every action."""
     import sys
