@@ -199,6 +199,92 @@ def run_grouped(args, sg, torch, ctx, stream):
     return res
 
 
+def sawtooth(tf, Ns, tile_n):
+    """Sawtooth of a fine-N TFLOPs line (Sec. 8.3, Table 13).  The line is detrended by a centred
+    moving average over one tile width; then
+      * period: the shortest lag (a multiple of the N step, 64..512) whose autocorrelation of the
+        detrended line is within 90 % of the highest;
+      * valley residue: the N mod tile_n whose detrended mean is lowest, and its depth (TFLOP/s
+        below the line's mean);
+      * valleys: strict interior local minima, their median spacing and the share of them at the
+        valley residue."""
+    tf = np.asarray(tf, dtype=np.float64)
+    step = int(Ns[1] - Ns[0])
+    w = max(3, tile_n // step)
+    pad = np.pad(tf, (w, w), mode="edge")
+    trend = np.convolve(pad, np.ones(2 * w + 1) / (2 * w + 1), mode="same")[w:-w]
+    d = tf - trend
+    lags = [L for L in range(64, 513, step) if L // step < len(d) - 4]
+    ac = [float(np.corrcoef(d[:-(L // step)], d[L // step:])[0, 1]) for L in lags]
+    # the fundamental: the shortest lag within 90 % of the best correlation (a multiple of the
+    # period correlates as well as the period itself)
+    period = min(L for L, c in zip(lags, ac) if c >= 0.9 * max(ac)) if lags else None
+    res = (np.asarray(Ns) % tile_n).astype(int)
+    prof = {int(r): float(d[res == r].mean()) for r in np.unique(res)}
+    vres = min(prof, key=prof.get)
+    v = [i for i in range(1, len(tf) - 1) if tf[i] < tf[i - 1] and tf[i] < tf[i + 1]]
+    share = (sum(1 for i in v if int(Ns[i]) % tile_n == vres) / len(v)) if v else None
+    return {"period": period, "period_autocorr": max(ac) if ac else None,
+            "valley_residue": vres, "valley_depth": -prof[vres], "valleys": len(v),
+            "valley_spacing_median": float(np.median(np.diff([Ns[i] for i in v]))) if len(v) > 1 else None,
+            "valleys_at_residue": share}
+
+
+def run_finen(args, sg, torch, ctx, stream):
+    """Sec. 8.3-8.4 on MI355X: fine-N sweeps (M = K = 4096, N = 32..4096 step 32) of every tile and
+    of the best-of-N envelope; sawtooth period and valley position per tile (Table 13); the DP's
+    T0 -> T1 (pad) and T2 (split + pad) applied to each line (Table 14)."""
+    M = K = 4096
+    step, n = 32, 128
+    Ns = np.arange(1, n + 1) * step
+    pool = 4096 * 4096
+    A = torch.empty(pool, dtype=torch.bfloat16, device="cuda")
+    B = torch.empty(pool, dtype=torch.bfloat16, device="cuda")
+    C = torch.empty(pool, dtype=torch.bfloat16, device="cuda")
+    sg.fill_bf16(A, 2, 0)
+    sg.fill_bf16(B, 2, 1)
+    torch.cuda.synchronize()
+    variants = [int(v) for v in args.variants.split(",")]
+    order = np.random.default_rng(args.order_seed).permutation(n)
+    shapes = [(M, int(Ns[i]), K) for i in order]
+    T0 = np.zeros((len(variants), n))
+    for r, v in enumerate(variants):
+        sec = ctx.sweep(shapes, A, B, C, mode=sg.MODE_VARIANT, variant=v, c_dtype=sg.BF16,
+                        warmup=args.shape_warmup, reps=args.reps, stream=stream)
+        T0[r, order] = sec
+    fl = 2.0 * M * Ns * K
+
+    def line_stats(rows, vids):
+        t = sg.Table.from_t0(step, 1, n, 1, rows.reshape(len(vids), 1, n, 1), vids)
+        t0, t1, t2 = (t.values(w).reshape(n) for w in (0, 1, 2))
+        out = {}
+        for name, sec in (("T0", t0), ("T1", t1), ("T2", t2)):
+            tf = fl / sec / 1e12
+            out[name] = {"mean": float(tf.mean()), "min": float(tf.min()), "roughness": sg.roughness(tf)}
+        out["T1_roughness_reduction"] = 1.0 - out["T1"]["roughness"] / out["T0"]["roughness"]
+        out["T2_roughness_reduction"] = 1.0 - out["T2"]["roughness"] / out["T0"]["roughness"]
+        return out, fl / t0 / 1e12
+
+    res = {"M": M, "K": K, "N": "32..4096 step 32", "tiles": {}}
+    seen = set()
+    for r, v in enumerate(variants):
+        vi = sg.variant_info(v)
+        if vi.splits != 1 or (vi.bm, vi.bn) in seen:
+            continue
+        seen.add((vi.bm, vi.bn))
+        st, tf = line_stats(T0[r:r + 1], [v])
+        st.update(sawtooth(tf, Ns, vi.bn))
+        st["tile"] = "%dx%d" % (vi.bm, vi.bn)
+        res["tiles"][vi.name] = st
+        log("fine-N %s: mean %.1f, roughness %.2f -> T1 %.2f; period %s, valleys at N mod %d = %s"
+            % (vi.name, st["T0"]["mean"], st["T0"]["roughness"], st["T1"]["roughness"], st["period"],
+               vi.bn, st["valley_residue"]))
+    env, tf = line_stats(T0, variants)
+    env.update(sawtooth(tf, Ns, 128))
+    res["best_of_%d" % len(variants)] = env
+    return res
+
+
 def run_offgrid(args, sg, torch, ctx, stream):
     """Config 3: 4,096 GEMMs with M, N, K ~ U{1..8192} (seed 3), BF16 out.  The dispatch table is
     measured on a step-512 grid {512..8192}^3 (4,096 cells; a step-128 grid to 8192 would be
@@ -282,9 +368,10 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--dump", default=None, help="write per-shape arrays (.npz) here")
-    ap.add_argument("--workload", choices=["sweep", "grouped", "serve", "offgrid"], default="sweep",
+    ap.add_argument("--workload", choices=["sweep", "grouped", "serve", "offgrid", "fineN"], default="sweep",
                     help="sweep: the landscape (headline) plus a serving leg; grouped: config 4; "
-                         "serve: config 5 at its full duration")
+                         "serve: config 5 at its full duration; offgrid: config 3; fineN: the "
+                         "fine-N cross-tile sweep")
     ap.add_argument("--groups", type=int, default=512)
     ap.add_argument("--serve-rate", type=float, default=2000.0)
     ap.add_argument("--serve-seconds", type=float, default=None,
@@ -332,6 +419,17 @@ def main():
                                 "N(0,0.02) BF16, BF16 out, HBM budget %d GiB"
                                 % (args.serve_rate, args.serve_seconds, args.serve_budget_gb)},
             serving=res, **common)), flush=True)
+        return
+    if args.workload == "fineN":
+        res = run_finen(args, sg, torch, ctx, stream)
+        env = res["best_of_%d" % len(args.variants.split(","))]
+        print(json.dumps(dict(
+            metric="fine-N best-of-N envelope roughness after DP padding (T1)",
+            value=env["T1"]["roughness"], unit="TFLOPs/step", higher_is_better=False,
+            ms_per_step=None,
+            config={"workload": "fine-N sweep: M = K = 4096, N = 32..4096 step 32, BF16 NN, BF16 out, "
+                                "every tile of the variant set and their best-of envelope"},
+            fine_n=res, **common)), flush=True)
         return
     if args.workload == "offgrid":
         res = run_offgrid(args, sg, torch, ctx, stream)
