@@ -298,8 +298,14 @@ __device__ __forceinline__ void tile_body_dma(const KArgs& p, const int m0, cons
             compute(kt % S, false, 0, 0);
         }
     }
+    // Tiles up to 128x128 write interior, unfused results straight from the accumulators
+    // (no barrier, no LDS round trip: it pays most at small K, where the epilogue is a large
+    // share of the tile).  The 256-wide tiles keep the LDS-staged epilogue: the direct stores
+    // raise them past 256 VGPRs and halve their occupancy.  A caller that runs tiles back to
+    // back must put a barrier before the next tile's loads, as the persistent kernel does.
+    if constexpr (T::SMALL)
+        if (epilogue_direct<BM, BN>(p, m0, n0, kz, acc)) return;
     __syncthreads();                            // ring no longer read: the epilogue reuses it
-
     epilogue<BM, BN>(p, m0, n0, kz, smem, acc);
 }
 
