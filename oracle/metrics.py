@@ -1,6 +1,7 @@
 """Landscape metrics -- oracle, test infrastructure only.
 
 Definitions of the paper's Sec. 2 (its closing measurement definitions) and Sec. 8.5, Table 17 (3-D aggregate),
+the four-surface decomposition of Sec. 4 (compute, memory, GEMM, overhead; Fig. 6, Table 3),
 the ideal compute landscape and the first-principles optimal of Sec. 9, and the attainment /
 roughness-ratio grading of Sec. 10 (Kernel Optimality Levels).
 """
@@ -47,6 +48,51 @@ def aggregate_3d(tf_mnk: np.ndarray):
     rK = roughness_along(tf, 2)
     return {"mean": float(tf.mean()), "peak": float(tf.max()), "roughness_m": rM,
             "roughness_n": rN, "roughness_k": rK, "roughness_3d": (rM + rN + rK) / 3.0}
+
+
+# Sec. 4: the four surfaces over one grid.  t_memory is measured (a kernel that moves the GEMM's
+# operands and result with no matrix work), t_gemm is measured; the other two follow from them.
+def compute_time(M: int, N: int, K: int, peak_tflops: float) -> float:
+    """Compute surface (Sec. 4.1): the useful FLOP 2MNK at the dense peak; tile-independent."""
+    return 2.0 * M * N * K / (peak_tflops * 1e12)
+
+
+def overhead_time(t_gemm: float, t_compute: float, t_memory: float) -> float:
+    """Overhead surface (Sec. 4.1): the GEMM time beyond the larger of compute and memory time."""
+    return t_gemm - max(t_compute, t_memory)
+
+
+def traffic_bytes(M: int, N: int, K: int, c_bytes: int = 2) -> float:
+    """Bytes of a GEMM that reads A and B once (BF16) and writes C once (c_bytes per element)."""
+    return 2.0 * M * K + 2.0 * K * N + float(c_bytes) * M * N
+
+
+def decompose(shapes, t_gemm, t_memory, peak_tflops: float, bw_gbs: float, c_bytes: int = 2):
+    """Sec. 4 over a list of (M, N, K) shapes with measured GEMM and memory times (seconds).
+
+    Returns per-shape compute and overhead times and the summary:
+      overhead_share -- mean over shapes of t_overhead / t_gemm (the stacked view of Fig. 6);
+      cb_bandwidth   -- fraction of shapes compute-bound against bandwidth bw_gbs:
+                        t_compute >= traffic_bytes / bw (Table 3, a bandwidth row);
+      cb_measured    -- fraction with t_compute >= t_memory (against the measured memory time).
+    """
+    t_comp, t_over = [], []
+    share = 0.0
+    cb_bw = 0
+    cb_meas = 0
+    for (M, N, K), tg, tm in zip(shapes, t_gemm, t_memory):
+        tc = compute_time(M, N, K, peak_tflops)
+        to = overhead_time(tg, tc, tm)
+        t_comp.append(tc)
+        t_over.append(to)
+        share += to / tg
+        if tc >= traffic_bytes(M, N, K, c_bytes) / (bw_gbs * 1e9):
+            cb_bw += 1
+        if tc >= tm:
+            cb_meas += 1
+    n = len(t_comp)
+    return {"t_compute": t_comp, "t_overhead": t_over, "overhead_share": share / n,
+            "cb_bandwidth": cb_bw / n, "cb_measured": cb_meas / n}
 
 
 def ideal_tflops(M: int, N: int, peak: float, cores: int, tile: int) -> float:

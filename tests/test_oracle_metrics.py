@@ -127,3 +127,76 @@ def test_kol_grade_on_hand_landscapes():
     A[:, 1::2, :] -= 30.0                       # a sawtooth along N
     g = metrics.kol_grade(A, O)
     assert g["rho"] > 1.0 and g["tau"] < 1.0
+
+
+# ---- Sec. 4 four-surface decomposition ------------------------------------------------------
+
+def test_compute_surface_has_no_texture():
+    """The compute surface is the useful FLOP at the dense peak: its throughput is the peak at
+    every shape, and along N its time grows by the same amount each step (Fig. 5, smooth)."""
+    rng = np.random.default_rng(41)
+    for _ in range(50):
+        M, N, K = (int(x) for x in rng.integers(1, 9000, 3))
+        t = metrics.compute_time(M, N, K, 2516.6)
+        assert metrics.tflops(M, N, K, t) == pytest.approx(2516.6, rel=1e-12)
+    t_line = [metrics.compute_time(2048, n, 1024, 116.5) for n in range(128, 4097, 128)]
+    steps = np.diff(t_line)
+    assert np.allclose(steps, 2.0 * 2048 * 128 * 1024 / 116.5e12, rtol=1e-12, atol=0)
+
+
+def test_overhead_surface_special_cases():
+    # a GEMM that takes exactly its compute (or memory) time has no overhead
+    assert metrics.overhead_time(3.0, 3.0, 1.0) == 0.0
+    assert metrics.overhead_time(3.0, 1.0, 3.0) == 0.0
+    # beyond the larger of the two, whichever it is
+    assert metrics.overhead_time(5.0, 1.0, 3.0) == 2.0
+    assert metrics.overhead_time(5.0, 4.0, 3.0) == 1.0
+    # a measured memory time above the GEMM's own gives a negative overhead, kept as is
+    assert metrics.overhead_time(2.0, 1.0, 2.5) == -0.5
+
+
+def test_overhead_share_of_a_constant_fraction():
+    """If every GEMM spends the fraction f of its time beyond max(compute, memory) -- the
+    paper's constant 32 % floor of Fig. 6 -- the mean share is f."""
+    rng = np.random.default_rng(43)
+    shapes = [tuple(int(x) for x in rng.integers(128, 4097, 3)) for _ in range(200)]
+    t_mem = [float(x) for x in rng.uniform(1e-6, 1e-3, len(shapes))]
+    f = 0.32
+    t_gemm = [max(metrics.compute_time(*s, 2516.6), tm) / (1.0 - f) for s, tm in zip(shapes, t_mem)]
+    d = metrics.decompose(shapes, t_gemm, t_mem, 2516.6, 8000.0)
+    assert d["overhead_share"] == pytest.approx(f, abs=1e-12)
+    assert all(o > 0 for o in d["t_overhead"])
+
+
+def test_compute_bound_squares_closed_form():
+    """A square n^3 GEMM moves (4 + c) n^2 bytes for 2 n^3 FLOP, so it is compute-bound against
+    bandwidth BW exactly when n >= (4 + c) P / (2 BW): on MI355X (2,516.6 TFLOP/s, 8 TB/s) n >= 943.7
+    with BF16 output (25 of the 32 step-128 squares) and n >= 1258.3 with FP32 (23 of 32)."""
+    sq = [(n, n, n) for n in range(128, 4097, 128)]
+    ones = [1.0] * len(sq)
+    assert metrics.decompose(sq, ones, ones, 2516.6, 8000.0, c_bytes=2)["cb_bandwidth"] == 25 / 32
+    assert metrics.decompose(sq, ones, ones, 2516.6, 8000.0, c_bytes=4)["cb_bandwidth"] == 23 / 32
+
+
+def test_compute_bound_is_intensity_above_the_ridge():
+    """Compute-bound against a bandwidth is the roofline statement: arithmetic intensity
+    2MNK / bytes at or above the ridge P / BW."""
+    rng = np.random.default_rng(47)
+    shapes = [tuple(int(x) for x in rng.integers(1, 8193, 3)) for _ in range(400)]
+    for P, BW in ((2516.6, 8000.0), (116.5, 456.0), (100.0, 1e9)):
+        ridge = P * 1e12 / (BW * 1e9)
+        expect = sum(2.0 * M * N * K / (2.0 * M * K + 2.0 * K * N + 2.0 * M * N) >= ridge * (1 - 1e-12)
+                     for M, N, K in shapes) / len(shapes)
+        ones = [1.0] * len(shapes)
+        assert metrics.decompose(shapes, ones, ones, P, BW)["cb_bandwidth"] == pytest.approx(expect)
+    # with unlimited bandwidth every shape is compute-bound
+    assert metrics.decompose(shapes, ones, ones, 2516.6, 1e30)["cb_bandwidth"] == 1.0
+
+
+def test_compute_bound_against_measured_memory_time():
+    rng = np.random.default_rng(53)
+    shapes = [tuple(int(x) for x in rng.integers(128, 4097, 3)) for _ in range(300)]
+    r = rng.uniform(0.5, 2.0, len(shapes))
+    t_mem = [metrics.compute_time(*s, 2516.6) * float(x) for s, x in zip(shapes, r)]
+    d = metrics.decompose(shapes, [1.0] * len(shapes), t_mem, 2516.6, 8000.0)
+    assert d["cb_measured"] == pytest.approx(float(np.mean(r <= 1.0)))
