@@ -285,6 +285,108 @@ def run_finen(args, sg, torch, ctx, stream):
     return res
 
 
+def stream_bandwidth(torch, mib: int = 1024) -> float:
+    """Measured streaming bandwidth (GB/s): a plain device copy of `mib` MiB, best of five,
+    counting the bytes read and written."""
+    src = torch.ones(mib << 18, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    best = float("inf")
+    for _ in range(5):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        e1.synchronize()
+        best = min(best, e0.elapsed_time(e1) * 1e-3)
+    del src, dst
+    return 2.0 * (mib << 20) / best / 1e9
+
+
+def run_decomp(args, sg, torch, ctx, stream):
+    """Sec. 4 on MI355X: the four surfaces over the landscape grid for each tile kernel (its
+    one-split variant) -- GEMM time (the kernel), memory time (its memory-only twin: the same
+    loads, waits and stores with no matrix-core work, at the same occupancy), compute time
+    2MNK / peak and overhead = GEMM - max(compute, memory); the stacked view along N at
+    M = K = 4096 (Fig. 6); the compute-/memory-bound split against the HBM specification, a
+    measured streaming bandwidth and the measured memory time (Table 3)."""
+    step, n = args.step, args.n
+    sizes = np.arange(1, n + 1) * step
+    pool = int(sizes[-1]) ** 2
+    A = torch.empty(pool, dtype=torch.bfloat16, device="cuda")
+    B = torch.empty(pool, dtype=torch.bfloat16, device="cuda")
+    C = torch.empty(pool, dtype=torch.bfloat16, device="cuda")
+    sg.fill_bf16(A, args.seed, 0)
+    sg.fill_bf16(B, args.seed, 1)
+    torch.cuda.synchronize()
+    bw_stream = stream_bandwidth(torch)
+    log("streaming copy bandwidth %.0f GB/s" % bw_stream)
+    grid = [(int(m), int(nn), int(k)) for m in sizes for nn in sizes for k in sizes]   # K fastest
+    order = np.random.default_rng(args.order_seed).permutation(len(grid))
+    shapes = [grid[i] for i in order]
+    Mg, Ng, Kg = (np.array([s[a] for s in grid], dtype=np.float64).reshape(n, n, n) for a in range(3))
+    traffic = 2.0 * Mg * Kg + 2.0 * Kg * Ng + 2.0 * Mg * Ng
+    variants = [int(v) for v in args.variants.split(",")]
+    res = {"grid": "{%d..%d}^3 step %d" % (step, step * n, step), "stream_bw_gbs": bw_stream,
+           "spec_bw_gbs": sg.MI355X["bw_gbs"], "peak_tflops": sg.MI355X["peak_tflops"], "tiles": {}}
+    seen = set()
+    for v in variants:
+        vi = sg.variant_info(v)
+        if vi.splits != 1 or (vi.bm, vi.bn) in seen:
+            continue
+        seen.add((vi.bm, vi.bn))
+        tg = np.empty(len(grid))
+        tm = np.empty(len(grid))
+        tg[order] = ctx.sweep(shapes, A, B, C, mode=sg.MODE_VARIANT, variant=v, c_dtype=sg.BF16,
+                              warmup=args.shape_warmup, reps=args.reps, stream=stream)
+        tm[order] = ctx.sweep(shapes, A, B, C, mode=sg.MODE_MEMORY, variant=v, c_dtype=sg.BF16,
+                              warmup=args.shape_warmup, reps=args.reps, stream=stream)
+        d = sg.decompose(grid, tg, tm, c_bytes=2)
+        d_stream = sg.decompose(grid, tg, tm, c_bytes=2, hw=dict(sg.MI355X, bw_gbs=bw_stream))
+        tc = d["t_compute"].reshape(n, n, n)
+        to = d["t_overhead"].reshape(n, n, n)
+        tg3, tm3 = tg.reshape(n, n, n), tm.reshape(n, n, n)
+        surf = {"compute": tc, "memory": tm3, "gemm": tg3, "overhead": to}
+        # texture of each time surface: N-axis roughness (us per step) on the K = max slice and
+        # over every line of the grid
+        rough = {}
+        for name, x in surf.items():
+            us = x * 1e6
+            rough[name] = {"slice_k_max": float(np.mean([sg.roughness(us[m, :, -1]) for m in range(n)])),
+                           "grid": sg.landscape_stats(us)["roughness_n"]}
+        line_share = to[-1, :, -1] / tg3[-1, :, -1]           # Fig. 6: M = K = max, N varies
+        mem_dom = tm3[-1, :, -1] > tc[-1, :, -1]
+        tiles_mn = np.ceil(Mg / vi.bm) * np.ceil(Ng / vi.bn)
+        loaded = tiles_mn * Kg * (vi.bm + vi.bn) * 2.0          # operand bytes into LDS per run
+        st = {
+            "mean_us": {k: float(x.mean() * 1e6) for k, x in surf.items()},
+            "overhead_share": d["overhead_share"],
+            "overhead_share_median": float(np.median(to / tg3)),
+            "compute_bound_spec_bw": d["cb_bandwidth"],
+            "compute_bound_stream_bw": d_stream["cb_bandwidth"],
+            "compute_bound_measured_memory": d["cb_measured"],
+            "roughness_us_per_step": rough,
+            "fig6_line": {"overhead_share_mean": float(line_share.mean()),
+                          "overhead_share_min": float(line_share.min()),
+                          "overhead_share_max": float(line_share.max()),
+                          "memory_dominant_points": int(mem_dom.sum()),
+                          "memory_dominant_up_to_n": int(sizes[mem_dom].max()) if mem_dom.any() else 0},
+            "twin_min_traffic_gbs": {"mean": float((traffic / tm3).mean() / 1e9),
+                                     "max": float((traffic / tm3).max() / 1e9)},
+            "twin_lds_load_tbs": {"mean": float((loaded / tm3).mean() / 1e12),
+                                  "max": float((loaded / tm3).max() / 1e12)},
+        }
+        res["tiles"][vi.name] = st
+        log("decomposition %s: mean us gemm %.1f memory %.1f compute %.1f overhead %.1f; overhead share "
+            "%.2f; compute-bound %.2f (spec BW) %.2f (stream BW) %.2f (measured memory)"
+            % (vi.name, st["mean_us"]["gemm"], st["mean_us"]["memory"], st["mean_us"]["compute"],
+               st["mean_us"]["overhead"], st["overhead_share"], st["compute_bound_spec_bw"],
+               st["compute_bound_stream_bw"], st["compute_bound_measured_memory"]))
+        if args.dump:
+            np.savez(args.dump + ".%s.npz" % vi.name, t_gemm=tg3, t_memory=tm3, t_compute=tc, t_overhead=to)
+    return res
+
+
 def run_offgrid(args, sg, torch, ctx, stream):
     """Config 3: 4,096 GEMMs with M, N, K ~ U{1..8192} (seed 3), BF16 out.  The dispatch table is
     measured on a step-512 grid {512..8192}^3 (4,096 cells; a step-128 grid to 8192 would be
@@ -368,10 +470,11 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--dump", default=None, help="write per-shape arrays (.npz) here")
-    ap.add_argument("--workload", choices=["sweep", "grouped", "serve", "offgrid", "fineN"], default="sweep",
+    ap.add_argument("--workload", choices=["sweep", "grouped", "serve", "offgrid", "fineN", "decomp"], default="sweep",
                     help="sweep: the landscape (headline) plus a serving leg; grouped: config 4; "
                          "serve: config 5 at its full duration; offgrid: config 3; fineN: the "
-                         "fine-N cross-tile sweep")
+                         "fine-N cross-tile sweep; decomp: the four-surface decomposition of "
+                         "every tile kernel with its memory-only twin")
     ap.add_argument("--groups", type=int, default=512)
     ap.add_argument("--serve-rate", type=float, default=2000.0)
     ap.add_argument("--serve-seconds", type=float, default=None,
@@ -430,6 +533,17 @@ def main():
             config={"workload": "fine-N sweep: M = K = 4096, N = 32..4096 step 32, BF16 NN, BF16 out, "
                                 "every tile of the variant set and their best-of envelope"},
             fine_n=res, **common)), flush=True)
+        return
+    if args.workload == "decomp":
+        res = run_decomp(args, sg, torch, ctx, stream)
+        plain = sg.variant_info(args.plain_variant).name
+        print(json.dumps(dict(
+            metric="four-surface decomposition: mean overhead share of the plain kernel's GEMM time",
+            value=res["tiles"][plain]["overhead_share"] if plain in res["tiles"] else None,
+            unit="fraction", higher_is_better=False, ms_per_step=None,
+            config={"workload": "landscape {%d..%d}^3 step %d, BF16 NN, BF16 out: every tile kernel "
+                                "and its memory-only twin" % (args.step, args.step * args.n, args.step)},
+            decomposition=res, **common)), flush=True)
         return
     if args.workload == "offgrid":
         res = run_offgrid(args, sg, torch, ctx, stream)

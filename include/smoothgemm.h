@@ -47,6 +47,12 @@ extern "C" {
 #define SG_MODE_BEST     2 /* best-of-N: per shape the variant with the least measured time        */
 #define SG_MODE_DP       3 /* dispatch-table plan: pad and/or split, each leaf on its best variant */
 #define SG_MODE_VARIANT  4 /* the variant given in sg_gemm_args.variant                            */
+/* Memory-only twin of sg_gemm_args.variant (the memory surface of Sec. 4): the same operand
+ * loads into LDS (with the same packing of unaligned operands), the same waits and barriers and
+ * the same stores of C as that variant's kernel, with the fragment reads and the matrix-core
+ * products left out.  C receives beta * C (zeros for beta = 0).  A measuring instrument, not a
+ * GEMM.  Operands that the direct-to-LDS path cannot load give SG_EINVAL. */
+#define SG_MODE_MEMORY   5
 
 /* ---- errors / version ------------------------------------------------------------------- */
 const char* sg_last_error(void);
@@ -80,7 +86,7 @@ typedef struct sg_gemm_args {
     int c_dtype;                  /* SG_F32 or SG_BF16                      */
     int beta;                     /* 0: C = A B;  1: C = A B + C (accumulate into C's old value) */
     int mode;                     /* SG_MODE_*                              */
-    int variant;                  /* used when mode == SG_MODE_VARIANT      */
+    int variant;                  /* used when mode == SG_MODE_VARIANT or SG_MODE_MEMORY */
 } sg_gemm_args;
 
 /* Extended call.  K == 0 gives C = beta * C.  SG_MODE_BEST / SG_MODE_DP without a table:
@@ -134,6 +140,25 @@ int sg_ideal_landscape(const struct sg_grid* grid, const sg_hw* hw, int tile, do
 int sg_optimal_landscape(const struct sg_grid* grid, const sg_hw* hw, const int* tiles, int ntiles,
                          int c_bytes, double* out);
 int sg_kol_grade(const double* actual, const double* optimal, int n_m, int n_n, int n_k, sg_kol* out);
+
+/* ---- four-surface decomposition (paper Sec. 4) ------------------------------------------------
+ * For n shapes with a measured GEMM time t_gemm[i] and a measured memory time t_memory[i]
+ * (seconds; e.g. sg_sweep of one variant in SG_MODE_VARIANT and in SG_MODE_MEMORY):
+ *   compute surface   t_compute[i]  = 2 M N K / (peak_tflops 1e12)  (useful FLOP at the dense
+ *                     peak, tile-independent, Sec. 4.1);
+ *   overhead surface  t_overhead[i] = t_gemm[i] - max(t_compute[i], t_memory[i]) (negative where
+ *                     the memory time exceeds the GEMM's own time);
+ * and out: overhead_share = mean over shapes of t_overhead / t_gemm (the stacked view of Fig. 6);
+ * cb_bandwidth = fraction of shapes with t_compute >= (2 M K + 2 K N + c_bytes M N) / bw_gbs
+ * (compute-bound against that bandwidth, Table 3); cb_measured = fraction with t_compute >=
+ * t_memory.  t_compute and t_overhead may be NULL.  Only hw->peak_tflops and hw->bw_gbs are
+ * read.  NULL inputs, n <= 0, an empty shape, a non-positive GEMM time or hardware value, or
+ * c_bytes <= 0 give SG_EINVAL. */
+typedef struct sg_decomp { double overhead_share, cb_bandwidth, cb_measured; } sg_decomp;
+struct sg_shape;
+int sg_decompose(const struct sg_shape* shapes, int64_t n, const double* t_gemm,
+                 const double* t_memory, const sg_hw* hw, int c_bytes, double* t_compute,
+                 double* t_overhead, sg_decomp* out);
 
 /* ---- sweep driver (paper Sec. 3 timing protocol, Sec. 5.4 randomized order) -----------------
  * Runs the n shapes in the order given (shuffle them for the randomized protocol) with

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(HERE, "libsmoothgemm.so")
 SG_OK, SG_EINVAL, SG_ENOMEM, SG_ENOTABLE, SG_EMISMATCH, SG_EHIP, SG_ERANGE, SG_EIO, SG_EAGAIN = \
     0, -1, -2, -3, -4, -5, -6, -7, -8
 F32, BF16 = 0, 1
-MODE_DEFAULT, MODE_PLAIN, MODE_BEST, MODE_DP, MODE_VARIANT = 0, 1, 2, 3, 4
+MODE_DEFAULT, MODE_PLAIN, MODE_BEST, MODE_DP, MODE_VARIANT, MODE_MEMORY = 0, 1, 2, 3, 4, 5
 ACT_AS_IS, ACT_PAD, ACT_SPLIT_M, ACT_SPLIT_N, ACT_SPLIT_K = 0, 1, 2, 3, 4
 
 _i64 = ctypes.c_int64
@@ -66,6 +66,10 @@ class sg_kol(ctypes.Structure):
     _fields_ = [("tau", _d), ("rho", _d), ("t_band", _i32), ("s_band", _i32), ("level", _i32)]
 
 
+class sg_decomp(ctypes.Structure):
+    _fields_ = [("overhead_share", _d), ("cb_bandwidth", _d), ("cb_measured", _d)]
+
+
 class sg_plan_rec(ctypes.Structure):
     _fields_ = [("action", _i32), ("arg", _i32), ("variant", _i32), ("t0", _d), ("t1", _d), ("t2", _d)]
 
@@ -88,6 +92,7 @@ _SIGS = {
     "sg_ideal_landscape": (_i32, [ctypes.POINTER(sg_grid), ctypes.POINTER(sg_hw), _i32, _p]),
     "sg_optimal_landscape": (_i32, [ctypes.POINTER(sg_grid), ctypes.POINTER(sg_hw), _p, _i32, _i32, _p]),
     "sg_kol_grade": (_i32, [_p, _p, _i32, _i32, _i32, ctypes.POINTER(sg_kol)]),
+    "sg_decompose": (_i32, [_p, _i64, _p, _p, ctypes.POINTER(sg_hw), _i32, _p, _p, ctypes.POINTER(sg_decomp)]),
     "sg_sweep": (_i32, [_p, _p, _i64, _i32, _i32, _i32, _i32, _i32, _p, _p, _p, _p, _p]),
     "sg_sweep_kernel_times": (_i32, [_p, _p, _p, _p]),
     "sg_table_from_t0": (_i32, [ctypes.POINTER(sg_grid), _p, _p, _i32, ctypes.POINTER(_p)]),
@@ -274,6 +279,24 @@ def optimal_landscape(step: int, n_m: int, n_n: int, n_k: int, tiles=(256, 128, 
     t = (ctypes.c_int * len(tiles))(*tiles)
     check(lib().sg_optimal_landscape(ctypes.byref(g), ctypes.byref(_hw(hw)), t, len(tiles), c_bytes, _arr(out)))
     return out
+
+
+def decompose(shapes, t_gemm, t_memory, c_bytes: int = 2, hw=MI355X) -> dict:
+    """Four-surface decomposition of measured GEMM and memory times (paper Sec. 4): per-shape
+    compute and overhead times (seconds) and the overhead share / compute-bound fractions."""
+    n = len(shapes)
+    sh = (sg_shape * n)(*[sg_shape(int(m), int(nn), int(k)) for (m, nn, k) in shapes])
+    tg = np.ascontiguousarray(t_gemm, dtype=np.float64)
+    tm = np.ascontiguousarray(t_memory, dtype=np.float64)
+    if tg.size != n or tm.size != n:
+        raise ValueError("one GEMM time and one memory time per shape")
+    tc = np.zeros(n, dtype=np.float64)
+    to = np.zeros(n, dtype=np.float64)
+    d = sg_decomp()
+    check(lib().sg_decompose(sh, n, _arr(tg), _arr(tm), ctypes.byref(_hw(hw)), c_bytes, _arr(tc),
+                             _arr(to), ctypes.byref(d)))
+    return {"t_compute": tc, "t_overhead": to, "overhead_share": d.overhead_share,
+            "cb_bandwidth": d.cb_bandwidth, "cb_measured": d.cb_measured}
 
 
 def kol_grade(actual: np.ndarray, optimal: np.ndarray) -> dict:

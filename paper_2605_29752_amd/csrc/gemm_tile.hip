@@ -44,6 +44,17 @@ __global__ __launch_bounds__(256) void sg_gemm_tile_dma(KArgs p) {
     tile_body_dma<BM, BN>(p, m0, n0, blockIdx.z, smem);
 }
 
+// Memory-only twin of sg_gemm_tile_dma: the same loads, waits and stores, no MFMA work.
+template <int BM, int BN>
+__global__ __launch_bounds__(256) void sg_gemm_tile_dma_mem(KArgs p) {
+    __shared__ __attribute__((aligned(1024))) uint16_t smem[dma_smem_bytes<BM, BN>() / 2];
+    int tm, tn;
+    tile_coords(p.tiles_m, p.tiles_n, tm, tn);
+    const int m0 = tm * BM, n0 = tn * BN;
+    if (m0 >= p.M || n0 >= p.N) return;
+    tile_body_dma<BM, BN, true>(p, m0, n0, blockIdx.z, smem);
+}
+
 template <int BM, int BN>
 __global__ __launch_bounds__(256) void sg_gemm_tile(KArgs p) {
     __shared__ __attribute__((aligned(16))) uint16_t smem[smem_elems<BM, BN>()];
@@ -209,6 +220,28 @@ static int launch_pack(const uint16_t* src, int64_t lds, int64_t rows, int64_t c
     return SG_OK;
 }
 
+// Dynamic LDS to reserve for the memory-only twin of a tile so that it runs as many
+// work-groups per CU as its GEMM kernel (the twin needs far fewer registers, which alone would
+// let more of it share a CU and overstate the bandwidth the GEMM's loads can draw).  -1 if the
+// occupancy query fails.
+template <int BM, int BN>
+static int twin_extra_lds() {
+    int occ_gemm = 0, occ_twin = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ_gemm, sg_gemm_tile_dma<BM, BN>, 256, 0) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ_twin, sg_gemm_tile_dma_mem<BM, BN>, 256, 0) != hipSuccess ||
+        occ_gemm < 1)
+        return -1;
+    if (occ_twin <= occ_gemm) return 0;
+    const int budget = 160 * 1024 - dma_smem_bytes<BM, BN>();
+    for (int extra = 1024; extra <= budget; extra += 1024) {
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ_twin, sg_gemm_tile_dma_mem<BM, BN>, 256,
+                                                         (size_t)extra) != hipSuccess)
+            return -1;
+        if (occ_twin <= occ_gemm) return extra;
+    }
+    return -1;
+}
+
 template <int BM, int BN>
 static int launch_tile(const LaunchDesc& d, int variant, void* ws, hipStream_t stream) {
     KArgs a;
@@ -268,7 +301,15 @@ static int launch_tile(const LaunchDesc& d, int variant, void* ws, hipStream_t s
     if (nwg > 0x7FFFFFFF) return fail(SG_EINVAL, "launch grid too large");
     dim3 grid((unsigned)nwg, 1, (unsigned)S), block(256);
     hipEvent_t stop1 = (S > 1) ? d.ev_mid : d.ev_stop;
-    if (aligned)
+    if (d.mem_only && !aligned)
+        return fail(SG_EINVAL, "memory-only twin: operands the direct-to-LDS path cannot load "
+                               "(an extent of 2^31 bytes or more, or no workspace to pack into)");
+    if (d.mem_only) {
+        static const int extra = twin_extra_lds<BM, BN>();
+        if (extra < 0) { (void)hipGetLastError(); return fail(SG_EHIP, "occupancy query for the memory-only twin failed"); }
+        hipExtLaunchKernelGGL((sg_gemm_tile_dma_mem<BM, BN>), grid, block, (size_t)extra, stream, start, stop1, 0, a);
+    }
+    else if (aligned)
         hipExtLaunchKernelGGL((sg_gemm_tile_dma<BM, BN>), grid, block, 0, stream, start, stop1, 0, a);
     else
         hipExtLaunchKernelGGL((sg_gemm_tile<BM, BN>), grid, block, 0, stream, start, stop1, 0, a);

@@ -1,7 +1,8 @@
 // First-principles GEMM landscape and Kernel Optimality Levels (paper Sec. 9 and Sec. 10): the
 // ideal ceiling, the optimal achievable landscape from datasheet integers (wave quantization
 // over the compute units, memory roofline), and the (tau, rho, level) grade of a measured
-// landscape against it.  Host code only.
+// landscape against it.  Also the four-surface decomposition of measured times (Sec. 4).
+// Host code only.
 #include <algorithm>
 #include <cmath>
 #include <limits>
@@ -100,6 +101,33 @@ int sg_kol_grade(const double* actual, const double* optimal, int nm, int nn, in
     out->t_band = throughput_band(out->tau);
     out->s_band = smoothness_band(out->rho);
     out->level = std::min(out->t_band, out->s_band);
+    return SG_OK;
+}
+
+int sg_decompose(const sg_shape* shapes, int64_t n, const double* t_gemm, const double* t_memory,
+                 const sg_hw* hw, int c_bytes, double* t_compute, double* t_overhead,
+                 sg_decomp* out) {
+    if (!shapes || n <= 0 || !t_gemm || !t_memory || !out || !hw || !(hw->peak_tflops > 0.0) ||
+        !(hw->bw_gbs > 0.0) || c_bytes <= 0)
+        return sg::fail(SG_EINVAL, "sg_decompose: bad argument");
+    const double peak = hw->peak_tflops * 1e12, bw = hw->bw_gbs * 1e9;
+    double share = 0.0;
+    int64_t cb_bw = 0, cb_meas = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        const double M = (double)shapes[i].M, N = (double)shapes[i].N, K = (double)shapes[i].K;
+        if (!(M > 0 && N > 0 && K > 0) || !(t_gemm[i] > 0.0))
+            return sg::fail(SG_EINVAL, "sg_decompose: empty shape or non-positive GEMM time");
+        const double tc = 2.0 * M * N * K / peak;
+        const double to = t_gemm[i] - std::max(tc, t_memory[i]);
+        if (t_compute) t_compute[i] = tc;
+        if (t_overhead) t_overhead[i] = to;
+        share += to / t_gemm[i];
+        if (tc >= (2.0 * M * K + 2.0 * K * N + (double)c_bytes * M * N) / bw) ++cb_bw;
+        if (tc >= t_memory[i]) ++cb_meas;
+    }
+    out->overhead_share = share / (double)n;
+    out->cb_bandwidth = (double)cb_bw / (double)n;
+    out->cb_measured = (double)cb_meas / (double)n;
     return SG_OK;
 }
 

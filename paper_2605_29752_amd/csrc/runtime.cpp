@@ -137,13 +137,14 @@ struct Problem {
     void* C; int64_t ldc;
     int c_bf16;
     int beta;
+    int mem_only;   // SG_MODE_MEMORY: every leaf runs its variant's memory-only twin
 };
 
 // Plan of one call as a list of leaves (single leaf for PLAIN / VARIANT / BEST).
 int make_plan(const sg_ctx* ctx, const Problem& pr, int mode, int variant, std::vector<Leaf>& leaves) {
     leaves.clear();
     if (mode == SG_MODE_DEFAULT) mode = ctx->table ? SG_MODE_DP : SG_MODE_PLAIN;
-    if (mode == SG_MODE_PLAIN || mode == SG_MODE_VARIANT) {
+    if (mode == SG_MODE_PLAIN || mode == SG_MODE_VARIANT || mode == SG_MODE_MEMORY) {
         const int v = (mode == SG_MODE_PLAIN) ? ctx->plain_variant : variant;
         if (v < 0 || v >= kNumVariants) return fail(SG_EINVAL, "variant out of range");
         leaves.push_back(Leaf{0, 0, 0, pr.M, pr.N, pr.K, pr.M, pr.N, pr.K, v, true, true});
@@ -191,6 +192,7 @@ int run_leaf(const Problem& pr, const Leaf& L, void* ws, size_t acc_bytes, hipSt
     d.ev_start = ev_start;
     d.ev_mid = ev_mid;
     d.ev_stop = ev_stop;
+    d.mem_only = pr.mem_only;
     d.M = L.m; d.N = L.n; d.K = L.k; d.Ml = L.Ml; d.Nl = L.Nl; d.Kl = L.Kl;
     d.A = pr.A + L.m0 * pr.lda + L.k0; d.lda = pr.lda;
     d.B = pr.B + L.k0 * pr.ldb + L.n0; d.ldb = pr.ldb;
@@ -235,7 +237,7 @@ int validate(const sg_gemm_args* a) {
     if (a->M < 0 || a->N < 0 || a->K < 0) return fail(SG_EINVAL, "negative dimension");
     if (a->c_dtype != SG_F32 && a->c_dtype != SG_BF16) return fail(SG_EINVAL, "bad c_dtype");
     if (a->beta != 0 && a->beta != 1) return fail(SG_EINVAL, "beta must be 0 or 1");
-    if (a->mode < SG_MODE_DEFAULT || a->mode > SG_MODE_VARIANT) return fail(SG_EINVAL, "bad mode");
+    if (a->mode < SG_MODE_DEFAULT || a->mode > SG_MODE_MEMORY) return fail(SG_EINVAL, "bad mode");
     if (a->M == 0 || a->N == 0) return SG_OK;
     if (!a->C) return fail(SG_EINVAL, "NULL C with non-zero size");
     if (a->ldc < a->N) return fail(SG_EINVAL, "ldc < N");
@@ -265,7 +267,7 @@ int gemm_impl(sg_ctx* ctx, const sg_gemm_args* a, hipStream_t s, std::vector<Lea
         return SG_OK;
     }
     Problem pr{a->M, a->N, a->K, (const uint16_t*)a->A, a->lda, (const uint16_t*)a->B, a->ldb,
-               a->C, a->ldc, a->c_dtype == SG_BF16, a->beta};
+               a->C, a->ldc, a->c_dtype == SG_BF16, a->beta, a->mode == SG_MODE_MEMORY};
     std::vector<Leaf> local;
     std::vector<Leaf>& leaves = keep ? *keep : local;
     rc = make_plan(ctx, pr, a->mode, a->variant, leaves);
@@ -539,7 +541,7 @@ extern "C" int sg_sweep(sg_ctx* ctx, const sg_shape* shapes, int64_t n, int mode
         const sg_shape& sh = shapes[i];
         if (sh.M <= 0 || sh.N <= 0 || sh.K <= 0) return fail(SG_EINVAL, "sg_sweep: empty shape");
         Problem pr{sh.M, sh.N, sh.K, (const uint16_t*)A_pool, sh.K, (const uint16_t*)B_pool, sh.N,
-                   C_pool, sh.N, c_dtype == SG_BF16, 0};
+                   C_pool, sh.N, c_dtype == SG_BF16, 0, mode == SG_MODE_MEMORY};
         int rc = make_plan(ctx, pr, mode, variant, leaves);
         if (rc) return rc;
         if (i == 0) {
@@ -583,7 +585,7 @@ int measure_t0(sg_ctx* ctx, const std::vector<sg_shape>& order, const std::vecto
     for (size_t i = 0; i < order.size(); ++i) {
         const sg_shape& sh = order[i];
         Problem pr{sh.M, sh.N, sh.K, (const uint16_t*)A_pool, sh.K, (const uint16_t*)B_pool, sh.N,
-                   C_pool, sh.N, c_dtype == SG_BF16, 0};
+                   C_pool, sh.N, c_dtype == SG_BF16, 0, 0};
         for (int v = 0; v < nvar; ++v) {
             leaves[0] = Leaf{0, 0, 0, sh.M, sh.N, sh.K, sh.M, sh.N, sh.K, variants[v], true, true};
             if (i == 0 && v == 0) {

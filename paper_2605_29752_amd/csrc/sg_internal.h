@@ -37,6 +37,7 @@ struct LaunchDesc {
     // tile kernel, ev_mid at its end when a split-K reduction follows, ev_stop at the end of
     // the launch's last kernel.
     hipEvent_t ev_start = nullptr, ev_mid = nullptr, ev_stop = nullptr;
+    int mem_only = 0;              // 1: run the tile's memory-only twin (no MFMA work, C = addend or 0)
 };
 
 enum { ADD_NONE = 0, ADD_F32 = 1, ADD_BF16 = 2 };

@@ -108,7 +108,11 @@ __device__ __forceinline__ void dma16(const i32x4_t rsrc, uint32_t voffset, uint
         : "memory");
 }
 
-template <int BM, int BN>
+// MEM = true gives the memory-only twin of the tile (the paper's memory surface, Sec. 4): the
+// same operand loads into the same ring, the same waits and barriers, and the same stores of C,
+// with the fragment reads and the matrix-core products left out (C is written as zeros, plus
+// the addend if one is fused).
+template <int BM, int BN, bool MEM = false>
 __device__ __forceinline__ void tile_body_dma(const KArgs& p, const int m0, const int n0, const int kz,
                                               uint16_t* __restrict__ smem) {
     using T = DmaTile<BM, BN>;
@@ -209,6 +213,13 @@ __device__ __forceinline__ void tile_body_dma(const KArgs& p, const int m0, cons
     // faster for them (the two-stage 256 x 128 ring needs its loads out as early as possible,
     // and the smaller tiles' rows are too short to cover a load's issue).
     auto compute = [&](int slot, bool issue_next, int kt_next, int slot_next) {
+      if constexpr (MEM) {
+        // the loads the MFMA rows would carry go out in one burst
+        if constexpr (SPREAD)
+            if (issue_next)
+#pragma unroll
+                for (int d = 0; d < PER_STAGE; ++d) issue_one(kt_next, slot_next, d);
+      } else {
         const char* stage = (const char*)smem + slot * T::STAGE_BYTES;
 #pragma unroll
         for (int h = 0; h < T::SUB; ++h) {
@@ -253,6 +264,7 @@ __device__ __forceinline__ void tile_body_dma(const KArgs& p, const int m0, cons
             }
             __builtin_amdgcn_s_setprio(0);
         }
+      }
     };
 
     // Step kt waits until this wave's loads of step kt have landed (at most `later` later

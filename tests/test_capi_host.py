@@ -173,6 +173,27 @@ def test_kol_grade_matches_oracle():
         sg.kol_grade(np.ones((2, 1, 1)), np.ones((2, 1, 1)))
 
 
+def test_decompose_matches_oracle():
+    rng = np.random.default_rng(17)
+    shapes = [tuple(int(x) for x in rng.integers(1, 8193, 3)) for _ in range(500)]
+    t_gemm = rng.uniform(1e-6, 2e-3, len(shapes))
+    t_mem = t_gemm * rng.uniform(0.2, 1.3, len(shapes))
+    for c_bytes, hw in ((2, sg.MI355X), (4, {"peak_tflops": 116.5, "cores": 20, "bw_gbs": 456.0})):
+        got = sg.decompose(shapes, t_gemm, t_mem, c_bytes=c_bytes, hw=hw)
+        want = om.decompose(shapes, list(t_gemm), list(t_mem), hw["peak_tflops"], hw["bw_gbs"], c_bytes)
+        np.testing.assert_allclose(got["t_compute"], want["t_compute"], rtol=1e-14, atol=0)
+        np.testing.assert_allclose(got["t_overhead"], want["t_overhead"], rtol=1e-12, atol=1e-20)
+        assert got["overhead_share"] == pytest.approx(want["overhead_share"], rel=1e-12)
+        assert got["cb_bandwidth"] == want["cb_bandwidth"]
+        assert got["cb_measured"] == want["cb_measured"]
+    with pytest.raises(sg.SGError):
+        sg.decompose([(0, 5, 5)], [1.0], [1.0])
+    with pytest.raises(sg.SGError):
+        sg.decompose([(5, 5, 5)], [0.0], [1.0])
+    with pytest.raises(sg.SGError):
+        sg.decompose([(5, 5, 5)], [1.0], [1.0], c_bytes=0)
+
+
 def test_synthetic_plans_cover_every_action():
     """The GPU plan-execution tests rely on these synthetic tables producing every action."""
     import sys
