@@ -387,6 +387,40 @@ def run_decomp(args, sg, torch, ctx, stream):
     return res
 
 
+EVIDENCE_SHAPES = [(4096, 4096, 4096), (3840, 2048, 4096), (4096, 4096, 128)]
+EVIDENCE_VARIANTS = [0, 8, 12, 16, 24]   # 256x256, 128x256, 128x128, 128x64, 64x64 (no split)
+
+
+def run_shapes(args, sg, torch, ctx, stream):
+    """Single-shape evidence: the square 4096^3, the paper's peak shape 3840 x 2048 x 4096 and the
+    small-K 4096 x 4096 x 128, each on several tile kernels and on their memory-only twins
+    (the launches a counter run attributes per kernel)."""
+    pool = 4096 * 4096
+    A = torch.empty(pool, dtype=torch.bfloat16, device="cuda")
+    B = torch.empty(pool, dtype=torch.bfloat16, device="cuda")
+    C = torch.empty(pool, dtype=torch.bfloat16, device="cuda")
+    sg.fill_bf16(A, args.seed, 0)
+    sg.fill_bf16(B, args.seed, 1)
+    torch.cuda.synchronize()
+    out = []
+    for (M, N, K) in EVIDENCE_SHAPES:
+        for v in EVIDENCE_VARIANTS:
+            name = sg.variant_info(v).name
+            t = ctx.sweep([(M, N, K)], A, B, C, mode=sg.MODE_VARIANT, variant=v, c_dtype=sg.BF16,
+                          warmup=args.shape_warmup, reps=args.reps, stream=stream)[0]
+            tm = ctx.sweep([(M, N, K)], A, B, C, mode=sg.MODE_MEMORY, variant=v, c_dtype=sg.BF16,
+                           warmup=args.shape_warmup, reps=args.reps, stream=stream)[0]
+            bytes_min = 2.0 * M * K + 2.0 * K * N + 2.0 * M * N
+            row = {"shape": [M, N, K], "variant": name, "gemm_us": t * 1e6, "twin_us": tm * 1e6,
+                   "tflops": 2.0 * M * N * K / t / 1e12,
+                   "frac_of_peak": 2.0 * M * N * K / t / 1e12 / sg.MI355X["peak_tflops"],
+                   "min_traffic_gbs": bytes_min / t / 1e9}
+            out.append(row)
+            log("%dx%dx%d %s: %.1f us, %.1f TFLOP/s (%.1f %% of peak); twin %.1f us"
+                % (M, N, K, name, row["gemm_us"], row["tflops"], 100 * row["frac_of_peak"], row["twin_us"]))
+    return out
+
+
 def run_offgrid(args, sg, torch, ctx, stream):
     """Config 3: 4,096 GEMMs with M, N, K ~ U{1..8192} (seed 3), BF16 out.  The dispatch table is
     measured on a step-512 grid {512..8192}^3 (4,096 cells; a step-128 grid to 8192 would be
@@ -470,11 +504,12 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--dump", default=None, help="write per-shape arrays (.npz) here")
-    ap.add_argument("--workload", choices=["sweep", "grouped", "serve", "offgrid", "fineN", "decomp"], default="sweep",
+    ap.add_argument("--workload", choices=["sweep", "grouped", "serve", "offgrid", "fineN", "decomp", "shapes"], default="sweep",
                     help="sweep: the landscape (headline) plus a serving leg; grouped: config 4; "
                          "serve: config 5 at its full duration; offgrid: config 3; fineN: the "
                          "fine-N cross-tile sweep; decomp: the four-surface decomposition of "
-                         "every tile kernel with its memory-only twin")
+                         "every tile kernel with its memory-only twin; shapes: 4096^3, 3840x2048x4096 "
+                         "and 4096x4096x128 on several tile kernels (counter evidence)")
     ap.add_argument("--groups", type=int, default=512)
     ap.add_argument("--serve-rate", type=float, default=2000.0)
     ap.add_argument("--serve-seconds", type=float, default=None,
@@ -533,6 +568,23 @@ def main():
             config={"workload": "fine-N sweep: M = K = 4096, N = 32..4096 step 32, BF16 NN, BF16 out, "
                                 "every tile of the variant set and their best-of envelope"},
             fine_n=res, **common)), flush=True)
+        return
+    if args.workload == "shapes":
+        if args.calibrate_copy > 0:
+            src = torch.ones(args.calibrate_copy << 18, dtype=torch.float32, device="cuda")
+            dst = torch.empty_like(src)
+            for _ in range(3):
+                dst.copy_(src)
+            torch.cuda.synchronize()
+            del src, dst
+        res = run_shapes(args, sg, torch, ctx, stream)
+        best = max(r["tflops"] for r in res if r["shape"] == [4096, 4096, 4096])
+        print(json.dumps(dict(
+            metric="BF16 TFLOP/s at 4096^3, best tile kernel", value=best, unit="TFLOP/s",
+            higher_is_better=True, ms_per_step=None,
+            config={"workload": "single shapes 4096^3, 3840x2048x4096, 4096x4096x128, BF16 NN, BF16 out, "
+                                "tile kernels and their memory-only twins"},
+            shapes=res, **common)), flush=True)
         return
     if args.workload == "decomp":
         res = run_decomp(args, sg, torch, ctx, stream)
