@@ -387,6 +387,116 @@ def run_decomp(args, sg, torch, ctx, stream):
     return res
 
 
+# ---- statistics of the memory study (Sec. 5): ranks, rank correlation, spread, drift --------
+def avg_ranks(x) -> np.ndarray:
+    x = np.asarray(x, dtype=np.float64)
+    order = np.argsort(x, kind="mergesort")
+    pos = np.empty(len(x))
+    pos[order] = np.arange(1, len(x) + 1)
+    _, inv, cnt = np.unique(x, return_inverse=True, return_counts=True)
+    return (np.bincount(inv, weights=pos) / cnt)[inv]        # ties share their mean position
+
+
+def spearman(x, y) -> float:
+    return float(np.corrcoef(avg_ranks(x), avg_ranks(y))[0, 1])
+
+
+def median_cv(t, keys) -> float:
+    """Median over keys of the coefficient of variation (population) of the times per key."""
+    _, inv = np.unique(np.asarray(keys), axis=0, return_inverse=True)
+    inv = inv.reshape(-1)
+    t = np.asarray(t, dtype=np.float64)
+    cnt = np.bincount(inv)
+    mean = np.bincount(inv, weights=t) / cnt
+    var = np.bincount(inv, weights=t * t) / cnt - mean * mean
+    return float(np.median(np.sqrt(np.maximum(var, 0.0)) / mean))
+
+
+def revisit_drift(t, keys, run_order) -> float:
+    """Mean over keys seen more than once of 1 - t(last run) / t(first run)."""
+    _, inv = np.unique(np.asarray(keys), axis=0, return_inverse=True)
+    inv = inv.reshape(-1)
+    t = np.asarray(t, dtype=np.float64)
+    o = np.asarray(run_order)
+    srt = np.lexsort((o, inv))                      # by key, then run order
+    k_s = inv[srt]
+    first = np.r_[True, k_s[1:] != k_s[:-1]]
+    last = np.r_[k_s[1:] != k_s[:-1], True]
+    t_first, t_last = t[srt][first], t[srt][last]
+    multi = (np.flatnonzero(last) - np.flatnonzero(first)) > 0
+    return float(np.mean(1.0 - t_last[multi] / t_first[multi]))
+
+
+def slowdown(t_co, t_iso) -> dict:
+    r = np.asarray(t_co, dtype=np.float64) / np.asarray(t_iso, dtype=np.float64)
+    return {"mean": float(r.mean()), "over_20": float((r > 1.2).mean()), "over_50": float((r > 1.5).mean())}
+
+
+def run_memory(args, sg, torch, ctx, stream):
+    """Sec. 5 on MI355X: FP32 buffer reads and writes over the landscape grid -- read A (M x K),
+    read B (K x N), read C and write D (M x N) -- each in a buffer allocated alone per measurement
+    (isolated) or alongside the other three (co-allocated), in randomized and in sequential
+    (nested M, N, K loop) order.  Reports Table 4 (co-allocation slowdown), the load / store
+    asymmetry, the warm-up drift and rank correlation with run order, and the spurious
+    dependence of read-A time on N (Fig. 9)."""
+    step, n = args.step, args.n
+    sizes = np.arange(1, n + 1) * step
+    grid = [(int(m), int(nn), int(k)) for m in sizes for nn in sizes for k in sizes]   # sequential
+    G = np.array(grid, dtype=np.float64)
+    order = np.random.default_rng(args.order_seed).permutation(len(grid))
+    rnd = [grid[i] for i in order]
+    e = 4
+    nbytes = {sg.MEM_READ_A: G[:, 0] * G[:, 2] * e, sg.MEM_READ_B: G[:, 2] * G[:, 1] * e,
+              sg.MEM_READ_C: G[:, 0] * G[:, 1] * e, sg.MEM_WRITE_D: G[:, 0] * G[:, 1] * e}
+    opname = {sg.MEM_READ_A: "read_A", sg.MEM_READ_B: "read_B", sg.MEM_READ_C: "read_C",
+              sg.MEM_WRITE_D: "write_D"}
+    T = {}
+    for op in (sg.MEM_READ_A, sg.MEM_READ_B, sg.MEM_READ_C, sg.MEM_WRITE_D):
+        for alloc, an in ((sg.MEM_ISOLATED, "isolated"), (sg.MEM_COALLOC, "coalloc")):
+            t = np.empty(len(grid))
+            t[order] = ctx.mem_sweep(rnd, op, alloc, elem_bytes=e, warmup=args.shape_warmup,
+                                     reps=args.reps, stream=stream)
+            T[(opname[op], an, "random")] = t
+            log("memory %s %s randomized: mean %.1f us" % (opname[op], an, t.mean() * 1e6))
+    for op, alloc, an in ((sg.MEM_READ_A, sg.MEM_ISOLATED, "isolated"), (sg.MEM_READ_A, sg.MEM_COALLOC, "coalloc"),
+                          (sg.MEM_READ_C, sg.MEM_ISOLATED, "isolated"), (sg.MEM_WRITE_D, sg.MEM_ISOLATED, "isolated")):
+        T[(opname[op], an, "sequential")] = ctx.mem_sweep(grid, op, alloc, elem_bytes=e,
+                                                          warmup=args.shape_warmup, reps=args.reps, stream=stream)
+        log("memory %s %s sequential done" % (opname[op], an))
+    run_rnd = np.empty(len(grid))
+    run_rnd[order] = np.arange(len(grid))
+    run_seq = np.arange(len(grid))
+    MK = G[:, [0, 2]]
+    bw = lambda op, key: float(np.mean(nbytes[op] / T[key]) / 1e9)
+    res = {"grid": "{%d..%d}^3 step %d" % (step, step * n, step), "elem_bytes": e, "reps": args.reps}
+    res["table4_coalloc_slowdown"] = {nm: slowdown(T[(nm, "coalloc", "random")], T[(nm, "isolated", "random")])
+                                     for nm in ("read_A", "read_B", "read_C", "write_D")}
+    res["load_store"] = {
+        "randomized": {"read_C_gbs": bw(sg.MEM_READ_C, ("read_C", "isolated", "random")),
+                       "write_D_gbs": bw(sg.MEM_WRITE_D, ("write_D", "isolated", "random"))},
+        "sequential": {"read_C_gbs": bw(sg.MEM_READ_C, ("read_C", "isolated", "sequential")),
+                       "write_D_gbs": bw(sg.MEM_WRITE_D, ("write_D", "isolated", "sequential"))}}
+    for k in ("randomized", "sequential"):
+        res["load_store"][k]["write_over_read"] = res["load_store"][k]["write_D_gbs"] / res["load_store"][k]["read_C_gbs"]
+    res["warmup"] = {
+        "sequential_isolated_read_A": {"spearman_run_order": spearman(T[("read_A", "isolated", "sequential")], run_seq),
+                                       "revisit_drift": revisit_drift(T[("read_A", "isolated", "sequential")], MK, run_seq)},
+        "randomized_isolated_read_A": {"spearman_run_order": spearman(T[("read_A", "isolated", "random")], run_rnd),
+                                       "revisit_drift": revisit_drift(T[("read_A", "isolated", "random")], MK, run_rnd)}}
+    res["read_A_vs_N"] = {}
+    for label, key in (("coalloc_sequential", ("read_A", "coalloc", "sequential")),
+                       ("isolated_sequential", ("read_A", "isolated", "sequential")),
+                       ("isolated_randomized", ("read_A", "isolated", "random"))):
+        res["read_A_vs_N"][label] = {"spearman_N": spearman(T[key], G[:, 1]), "median_cv_across_N": median_cv(T[key], MK),
+                                     "mean_gbs": bw(sg.MEM_READ_A, key)}
+    log("memory: co-allocation slowdown read A %.3f, write/read %.2f (randomized), read-A vs N rho %s"
+        % (res["table4_coalloc_slowdown"]["read_A"]["mean"], res["load_store"]["randomized"]["write_over_read"],
+           {k: round(v["spearman_N"], 3) for k, v in res["read_A_vs_N"].items()}))
+    if args.dump:
+        np.savez(args.dump + ".memory.npz", shapes=G, **{"_".join(k): v for k, v in T.items()})
+    return res
+
+
 EVIDENCE_SHAPES = [(4096, 4096, 4096), (3840, 2048, 4096), (4096, 4096, 128)]
 EVIDENCE_VARIANTS = [0, 8, 12, 16, 24]   # 256x256, 128x256, 128x128, 128x64, 64x64 (no split)
 
@@ -504,12 +614,13 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--dump", default=None, help="write per-shape arrays (.npz) here")
-    ap.add_argument("--workload", choices=["sweep", "grouped", "serve", "offgrid", "fineN", "decomp", "shapes"], default="sweep",
+    ap.add_argument("--workload", choices=["sweep", "grouped", "serve", "offgrid", "fineN", "decomp", "shapes", "memory"], default="sweep",
                     help="sweep: the landscape (headline) plus a serving leg; grouped: config 4; "
                          "serve: config 5 at its full duration; offgrid: config 3; fineN: the "
                          "fine-N cross-tile sweep; decomp: the four-surface decomposition of "
                          "every tile kernel with its memory-only twin; shapes: 4096^3, 3840x2048x4096 "
-                         "and 4096x4096x128 on several tile kernels (counter evidence)")
+                         "and 4096x4096x128 on several tile kernels (counter evidence); memory: the "
+                         "buffer read/write study (co-allocation, load/store, warm-up, order)")
     ap.add_argument("--groups", type=int, default=512)
     ap.add_argument("--serve-rate", type=float, default=2000.0)
     ap.add_argument("--serve-seconds", type=float, default=None,
@@ -568,6 +679,17 @@ def main():
             config={"workload": "fine-N sweep: M = K = 4096, N = 32..4096 step 32, BF16 NN, BF16 out, "
                                 "every tile of the variant set and their best-of envelope"},
             fine_n=res, **common)), flush=True)
+        return
+    if args.workload == "memory":
+        res = run_memory(args, sg, torch, ctx, stream)
+        print(json.dumps(dict(
+            metric="memory study: mean co-allocation slowdown of read A (randomized order)",
+            value=res["table4_coalloc_slowdown"]["read_A"]["mean"], unit="ratio", higher_is_better=False,
+            ms_per_step=None,
+            config={"workload": "FP32 buffer reads (A M x K, B K x N, C M x N) and writes (D M x N) over "
+                                "{%d..%d}^3 step %d, isolated vs co-allocated, randomized vs sequential"
+                                % (args.step, args.step * args.n, args.step)},
+            memory=res, **common)), flush=True)
         return
     if args.workload == "shapes":
         if args.calibrate_copy > 0:

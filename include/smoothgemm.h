@@ -181,6 +181,36 @@ int sg_sweep(sg_ctx* ctx, const sg_shape* shapes, int64_t n, int mode, int varia
  * sg_num_variants() entries. */
 int sg_sweep_kernel_times(const sg_ctx* ctx, int64_t* launches, double* seconds, double* flops);
 
+/* ---- memory-subsystem study (paper Sec. 5) -----------------------------------------------------
+ * Bandwidth microbenchmarks over the GEMM's buffers: read A (M x K), read B (K x N), read C and
+ * write D (M x N, the identical buffers of the load / store comparison), elem_bytes per element
+ * (the paper uses FP32 buffers: 4).
+ * sg_mem_read: streams `bytes` of the device buffer `buf` with 16-byte loads and folds every
+ *   32-bit word into an XOR; writes sg_mem_read_blocks(bytes) (at most 2048) partial XORs to
+ *   the device array `sink`, whose XOR is the XOR of all the buffer's words.
+ * sg_mem_write: stores 32-bit word i of the buffer (counting from its start) as
+ *   (i * 0x9E3779B1) ^ seed, modulo 2^32.
+ *   Both: `bytes` a non-negative multiple of 16, `buf` 16-byte aligned, else SG_EINVAL; async on
+ *   the stream.
+ * sg_mem_sweep: per shape, in the order given (sequential or shuffled, Sec. 5.4), allocates the
+ *   buffers -- the measured one alone (SG_MEM_ISOLATED, one allocation per measurement) or A, B,
+ *   C (M x N) and D in that order (SG_MEM_COALLOC, as the GEMM's operands sit together) --, runs
+ *   `op` once untimed (plus `warmup` untimed runs before the first shape) and `reps` times timed,
+ *   frees the buffers, and writes the mean seconds of a timed run to out_sec[i] (each run timed
+ *   by its own dispatch's timestamps).  Lengths are rounded up to 16 bytes.  Allocation failure:
+ *   SG_ENOMEM.  Synchronous (it waits for each shape's timing events). */
+#define SG_MEM_READ_A   0
+#define SG_MEM_READ_B   1
+#define SG_MEM_WRITE_D  2
+#define SG_MEM_READ_C   3
+#define SG_MEM_ISOLATED 0
+#define SG_MEM_COALLOC  1
+int64_t sg_mem_read_blocks(int64_t bytes);
+int sg_mem_read(const void* buf, int64_t bytes, uint32_t* sink, void* stream);
+int sg_mem_write(void* buf, int64_t bytes, uint32_t seed, void* stream);
+int sg_mem_sweep(sg_ctx* ctx, const sg_shape* shapes, int64_t n, int op, int alloc, int elem_bytes,
+                 int warmup, int reps, double* out_sec, void* stream);
+
 /* ---- dispatch table (paper Sec. 7.1) ---------------------------------------------------------
  * Grid: sizes (i + 1) * step for i < n_m (M axis), n_n (N axis), n_k (K axis).  T0 holds, per
  * variant and cell, measured seconds; best-of-N takes the per-cell minimum; T1 pads

@@ -21,6 +21,8 @@ SG_OK, SG_EINVAL, SG_ENOMEM, SG_ENOTABLE, SG_EMISMATCH, SG_EHIP, SG_ERANGE, SG_E
 F32, BF16 = 0, 1
 MODE_DEFAULT, MODE_PLAIN, MODE_BEST, MODE_DP, MODE_VARIANT, MODE_MEMORY = 0, 1, 2, 3, 4, 5
 ACT_AS_IS, ACT_PAD, ACT_SPLIT_M, ACT_SPLIT_N, ACT_SPLIT_K = 0, 1, 2, 3, 4
+MEM_READ_A, MEM_READ_B, MEM_WRITE_D, MEM_READ_C = 0, 1, 2, 3
+MEM_ISOLATED, MEM_COALLOC = 0, 1
 
 _i64 = ctypes.c_int64
 _i32 = ctypes.c_int
@@ -107,6 +109,10 @@ _SIGS = {
     "sg_table_save": (_i32, [_p, ctypes.c_char_p]),
     "sg_table_load": (_i32, [ctypes.c_char_p, _i32, ctypes.POINTER(_p)]),
     "sg_fill_bf16": (_i32, [_p, _i64, ctypes.c_uint64, ctypes.c_uint64, _i64, _i32, _d, _p]),
+    "sg_mem_read_blocks": (_i64, [_i64]),
+    "sg_mem_read": (_i32, [_p, _i64, _p, _p]),
+    "sg_mem_write": (_i32, [_p, _i64, ctypes.c_uint32, _p]),
+    "sg_mem_sweep": (_i32, [_p, _p, _i64, _i32, _i32, _i32, _i32, _i32, _p, _p]),
     "sg_group_plan_create": (_i32, [_p, _i32, _p, _i32, _p, _p, ctypes.POINTER(_p)]),
     "sg_group_plan_launch": (_i32, [_p, _p]),
     "sg_group_plan_update": (_i32, [_p, _p, _p]),
@@ -435,6 +441,15 @@ class Context:
         check(lib().gemm_bf16_nn_ex(self.handle, ctypes.byref(a), _stream_ptr(stream)))
         return C
 
+    def mem_sweep(self, shapes, op: int, alloc: int, *, elem_bytes: int = 4, warmup: int = 5,
+                  reps: int = 5, stream=None) -> np.ndarray:
+        """Memory-study sweep (paper Sec. 5): seconds per run of `op` on each shape's buffer."""
+        sh = (sg_shape * len(shapes))(*[sg_shape(int(m), int(n), int(k)) for (m, n, k) in shapes])
+        out = np.zeros(len(shapes), dtype=np.float64)
+        check(lib().sg_mem_sweep(self.handle, sh, len(shapes), op, alloc, elem_bytes, warmup, reps,
+                                 _arr(out), _stream_ptr(stream)))
+        return out
+
     def sweep(self, shapes, A_pool, B_pool, C_pool, *, mode=MODE_PLAIN, variant=0, c_dtype=BF16,
               warmup=5, reps=5, stream=None) -> np.ndarray:
         sh = (sg_shape * len(shapes))(*[sg_shape(int(m), int(n), int(k)) for (m, n, k) in shapes])
@@ -615,6 +630,23 @@ def fill_bf16(dst, seed: int, stream_id: int, *, offset: int = 0, kind: int = 0,
     check(lib().sg_fill_bf16(dst.data_ptr(), dst.numel(), seed, stream_id, offset, kind, scale,
                              _stream_ptr(stream)))
     return dst
+
+
+def mem_read_blocks(nbytes: int) -> int:
+    return int(lib().sg_mem_read_blocks(int(nbytes)))
+
+
+def mem_read(buf, sink, nbytes=None, stream=None):
+    """Stream-read a device tensor; `sink` (uint32-sized device tensor of at least
+    mem_read_blocks(nbytes) words) receives per-block XORs of its 32-bit words."""
+    nbytes = buf.numel() * buf.element_size() if nbytes is None else nbytes
+    check(lib().sg_mem_read(buf.data_ptr(), nbytes, sink.data_ptr(), _stream_ptr(stream)))
+
+
+def mem_write(buf, seed: int, nbytes=None, stream=None):
+    """Stream-write a device tensor: word i = (i * 0x9E3779B1) ^ seed (mod 2^32)."""
+    nbytes = buf.numel() * buf.element_size() if nbytes is None else nbytes
+    check(lib().sg_mem_write(buf.data_ptr(), nbytes, seed, _stream_ptr(stream)))
 
 
 def to_device_bf16(bits: np.ndarray, device="cuda"):

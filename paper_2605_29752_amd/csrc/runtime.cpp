@@ -562,6 +562,75 @@ extern "C" int sg_sweep(sg_ctx* ctx, const sg_shape* shapes, int64_t n, int mode
     return SG_OK;
 }
 
+extern "C" int sg_mem_sweep(sg_ctx* ctx, const sg_shape* shapes, int64_t n, int op, int alloc,
+                            int elem_bytes, int warmup, int reps, double* out_sec, void* stream) {
+    if (!ctx || (n > 0 && (!shapes || !out_sec))) return fail(SG_EINVAL, "sg_mem_sweep: NULL argument");
+    if (n < 0 || warmup < 0 || reps < 1) return fail(SG_EINVAL, "sg_mem_sweep: bad counts");
+    if (op != SG_MEM_READ_A && op != SG_MEM_READ_B && op != SG_MEM_READ_C && op != SG_MEM_WRITE_D)
+        return fail(SG_EINVAL, "sg_mem_sweep: bad op");
+    if (alloc != SG_MEM_ISOLATED && alloc != SG_MEM_COALLOC) return fail(SG_EINVAL, "sg_mem_sweep: bad alloc");
+    if (elem_bytes != 2 && elem_bytes != 4) return fail(SG_EINVAL, "sg_mem_sweep: elem_bytes must be 2 or 4");
+    for (int64_t i = 0; i < n; ++i)
+        if (shapes[i].M <= 0 || shapes[i].N <= 0 || shapes[i].K <= 0)
+            return fail(SG_EINVAL, "sg_mem_sweep: empty shape");
+    DeviceGuard guard(ctx->device);
+    hipStream_t s = (hipStream_t)stream;
+    int rc = ensure_events(ctx, 2 * (size_t)reps);
+    if (rc) return rc;
+    uint32_t* sink = nullptr;
+    if (hipMalloc((void**)&sink, 2048 * sizeof(uint32_t)) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(SG_ENOMEM, "sg_mem_sweep: sink allocation failed");
+    }
+    // Buffers of one shape: A (M x K), B (K x N), C and D (M x N); lengths rounded up to 16 bytes.
+    void* buf[4] = {nullptr, nullptr, nullptr, nullptr};
+    auto release = [&]() {
+        for (void*& b : buf)
+            if (b) { (void)hipFree(b); b = nullptr; }
+    };
+    auto run = [&](void* target, int64_t bytes, hipEvent_t e0, hipEvent_t e1) {
+        return op == SG_MEM_WRITE_D ? launch_mem_write(target, bytes, 0x5eedu, s, e0, e1)
+                                    : launch_mem_read(target, bytes, sink, s, e0, e1);
+    };
+    const int target_idx = op == SG_MEM_READ_A ? 0 : op == SG_MEM_READ_B ? 1 : op == SG_MEM_READ_C ? 2 : 3;
+    for (int64_t i = 0; i < n && rc == SG_OK; ++i) {
+        const sg_shape& sh = shapes[i];
+        int64_t len[4] = {sh.M * sh.K, sh.K * sh.N, sh.M * sh.N, sh.M * sh.N};
+        for (int64_t& l : len) l = (l * elem_bytes + 15) / 16 * 16;
+        // isolated: the measured buffer alone; co-allocated: A, B, C, D in that order
+        for (int b = 0; b < 4 && rc == SG_OK; ++b) {
+            if (alloc == SG_MEM_ISOLATED && b != target_idx) continue;
+            if (hipMalloc(&buf[b], (size_t)len[b]) != hipSuccess) {
+                (void)hipGetLastError();
+                buf[b] = nullptr;
+                rc = fail(SG_ENOMEM, "sg_mem_sweep: buffer allocation failed");
+            }
+        }
+        void* target = buf[target_idx];
+        const int64_t bytes = len[target_idx];
+        for (int w = 0; w < (i == 0 ? warmup : 0) + 1 && rc == SG_OK; ++w) rc = run(target, bytes, nullptr, nullptr);
+        for (int r = 0; r < reps && rc == SG_OK; ++r)
+            rc = run(target, bytes, ctx->events[2 * r], ctx->events[2 * r + 1]);
+        if (rc == SG_OK) {
+            hipError_t e = hipEventSynchronize(ctx->events[2 * reps - 1]);
+            double total = 0.0;
+            for (int r = 0; r < reps && e == hipSuccess; ++r) {
+                float ms = 0.f;
+                e = hipEventElapsedTime(&ms, ctx->events[2 * r], ctx->events[2 * r + 1]);
+                total += (double)ms * 1e-3;
+            }
+            if (e != hipSuccess) rc = hip_fail(e, "sg_mem_sweep timing");
+            else out_sec[i] = total / reps;
+        }
+        release();
+        if (rc == SG_OK && ctx->progress_every > 0 && (i + 1) % ctx->progress_every == 0)
+            std::fprintf(stderr, "[smoothgemm] memory sweep %lld / %lld shapes\n", (long long)(i + 1), (long long)n);
+    }
+    release();
+    (void)hipFree(sink);
+    return rc;
+}
+
 extern "C" int sg_sweep_kernel_times(const sg_ctx* ctx, int64_t* launches, double* seconds,
                                      double* flops) {
     if (!ctx) return fail(SG_EINVAL, "NULL ctx");

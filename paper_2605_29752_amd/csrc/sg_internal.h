@@ -21,6 +21,13 @@ int hip_fail(hipError_t e, const char* what);
         if (e_ != hipSuccess) return ::sg::hip_fail(e_, #call); \
     } while (0)
 
+// Buffer read / write kernels of the memory study (membench.hip).  Length a multiple of 16
+// bytes, 16-byte aligned buffer; the read writes mem_blocks(bytes) partial XORs to sink.
+int64_t mem_blocks(int64_t bytes);
+int launch_mem_read(const void* buf, int64_t bytes, uint32_t* sink, hipStream_t s, hipEvent_t start,
+                    hipEvent_t stop);
+int launch_mem_write(void* buf, int64_t bytes, uint32_t seed, hipStream_t s, hipEvent_t start, hipEvent_t stop);
+
 // One GEMM kernel launch of the tile family.
 //  data dims (M, N, K) bound every load and store; the launch covers (Ml, Nl) in whole tiles
 //  and runs the K loop over Kl >= K (padding: beyond K the operands read as zero).
