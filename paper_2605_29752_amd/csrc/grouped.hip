@@ -47,7 +47,7 @@ __global__ __launch_bounds__(256) void sg_gemm_grouped(const GroupProblem* __res
         const int local = t - q.tile_begin;
         const int tm = local % q.tiles_m;      // M fastest: consecutive tiles share a B panel
         const int tn = local / q.tiles_m;
-        KArgs a;
+        KArgs a{};
         a.A = q.A; a.B = q.B; a.C = q.C; a.add = nullptr;
         a.lda = q.lda; a.ldb = q.ldb; a.ldc = q.ldc; a.ldadd = 0; a.ws_slice = 0;
         a.M = q.M; a.N = q.N; a.K = q.K; a.Kl = q.K; a.k_chunk = ((q.K + kBK - 1) / kBK) * kBK;

@@ -38,11 +38,54 @@ def kernel_body(text, name):
     return text[start:end]
 
 
+def _accumulator_copies(body):
+    """AGPR-to-AGPR moves whose source is not a register just set to zero (a zero broadcast that
+    initialises accumulators is fine; a copy of live accumulator data is what to catch).  A
+    linear scan: an AGPR counts as zero from `v_accvgpr_write_b32 aN, 0` (or a move from a zero
+    register) until another instruction writes it."""
+    zero, bad = set(), []
+    for line in body.split("\n"):
+        ins = line.strip().split(None, 1)
+        if len(ins) < 2 or ins[0].startswith((";", ".")):
+            continue
+        ops = [o.strip() for o in ins[1].split(",")]
+        dst = ops[0]
+        regs = set()
+        m = re.fullmatch(r"a(\d+)", dst)
+        if m:
+            regs = {int(m.group(1))}
+        m = re.fullmatch(r"a\[(\d+):(\d+)\]", dst)
+        if m:
+            regs = set(range(int(m.group(1)), int(m.group(2)) + 1))
+        if ins[0] == "v_accvgpr_write_b32" and len(ops) > 1 and ops[1] == "0":
+            zero |= regs
+            continue
+        if ins[0].startswith("v_accvgpr_mov"):
+            src = re.fullmatch(r"a(\d+)", ops[1])
+            if src and int(src.group(1)) in zero:
+                zero |= regs
+                continue
+            bad.append(line.strip())
+        zero -= regs
+    return bad
+
+
 @pytest.mark.parametrize("bm,bn", TILES)
 def test_no_accumulator_copies(asm, bm, bn):
     body = kernel_body(asm, "_ZN2sg16sg_gemm_tile_dmaILi%dELi%dEEEvNS_5KArgsE" % (bm, bn))
     assert re.search(r"v_mfma_f32_16x16x32_bf16", body)
-    assert "v_accvgpr_mov" not in body, "accumulators copied between MFMAs"
+    bad = _accumulator_copies(body)
+    assert not bad, "accumulators copied between MFMAs: %s" % bad[:4]
+
+
+def test_accumulator_copy_scan_catches_copies():
+    """The scan accepts a zero broadcast and rejects a copy of live data."""
+    assert _accumulator_copies("\tv_accvgpr_write_b32 a0, 0\n\tv_accvgpr_mov_b32 a1, a0\n") == []
+    live = "\tv_mfma_f32_16x16x32_bf16 a[0:3], v[0:3], v[4:7], a[0:3]\n\tv_accvgpr_mov_b32 a4, a0\n"
+    assert _accumulator_copies(live) == ["v_accvgpr_mov_b32 a4, a0"]
+    rezeroed = ("\tv_accvgpr_write_b32 a0, 0\n\tv_mfma_f32_16x16x32_bf16 a[0:3], v[0:3], v[4:7], a[0:3]\n"
+                "\tv_accvgpr_mov_b32 a5, a0\n")
+    assert _accumulator_copies(rezeroed) == ["v_accvgpr_mov_b32 a5, a0"]
 
 
 @pytest.mark.parametrize("bm,bn", TILES)
