@@ -203,3 +203,16 @@ def test_synthetic_plans_cover_every_action():
         t, _ = _random_table(seed, shape, 64, variants)
         acts = {t.lookup(*[(c + 1) * 64 for c in cell])["action"] for cell in np.ndindex(shape)}
         assert acts == {0, 1, 2, 3, 4}
+
+
+def test_memory_study_host_contract():
+    """Block count of the streaming read, and arguments rejected before any device call."""
+    L = sg.lib()
+    assert L.sg_mem_read_blocks(0) == 1 and L.sg_mem_read_blocks(16) == 1
+    assert L.sg_mem_read_blocks(1 << 20) == 64          # 65,536 16-byte chunks / (256 lanes x 4)
+    assert L.sg_mem_read_blocks(1 << 30) == 2048        # capped at 8 work-groups per CU
+    assert L.sg_mem_read_blocks(-5) == 0
+    assert L.sg_mem_read(None, 20, None, None) == sg.SG_EINVAL       # not a multiple of 16
+    assert L.sg_mem_read(None, 32, None, None) == sg.SG_EINVAL       # NULL buffer
+    assert L.sg_mem_write(None, -16, 0, None) == sg.SG_EINVAL
+    assert L.sg_mem_sweep(None, None, 0, 0, 0, 4, 0, 1, None, None) == sg.SG_EINVAL
