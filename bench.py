@@ -79,10 +79,16 @@ def first_principles(sg, stack_secs, sizes, step, n):
 
 
 def kernel_source_hash() -> str:
+    """SHA-1 of the tile kernels' source with comments and whitespace removed, so that only a
+    change of the code itself retires recorded counter figures."""
     import hashlib
+    import re
     h = hashlib.sha1()
     for f in ("tile_body.h", "tile_body_dma.h", "gemm_tile.hip"):
-        h.update(open(os.path.join(ROOT, "paper_2605_29752_amd", "csrc", f), "rb").read())
+        text = open(os.path.join(ROOT, "paper_2605_29752_amd", "csrc", f)).read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(re.sub(r"\s+", " ", text).strip().encode())
     return h.hexdigest()
 
 

@@ -6,11 +6,15 @@
 // accumulators in registers.  Two bodies:
 //
 //  * aligned operands (leading dimensions, K and N multiples of 8, 16-byte bases: every shape
-//    of the landscape): tile_body_dma.h, operands loaded HBM -> LDS directly into a ring of four
-//    32-deep K stages, three stages of loads in flight, B fragments read with transposing LDS
-//    reads;
-//  * anything else: tile_body.h, element-wise predicated loads into registers, B transposed in
-//    registers, two padded LDS stages of 64-deep K steps.
+//    of the landscape), or operands first copied zero-padded into the workspace so that they
+//    are: tile_body_dma.h, operands loaded HBM -> LDS directly into a ring of K stages whose
+//    depth is chosen per tile (DmaTile), B fragments read with transposing LDS reads;
+//  * anything else (no workspace, or an operand extent beyond the loads' 31-bit offsets):
+//    tile_body.h, element-wise predicated loads into registers, B transposed in registers, two
+//    padded LDS stages of 64-deep K steps.
+//
+// Each direct-to-LDS kernel has a memory-only twin (sg_gemm_tile_dma_mem) with the same loads,
+// waits and stores and no matrix work: the measured memory surface of the paper's Sec. 4.
 //
 // The MFMA is issued with B^T as its first operand, so each lane ends up holding four
 // consecutive N columns of one C row and stores them as one vector.

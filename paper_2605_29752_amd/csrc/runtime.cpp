@@ -1,5 +1,6 @@
 // smoothgemm host runtime: contexts, the per-call GEMM entry points, plan execution, the sweep
-// driver and the landscape metrics.  The dispatch-table construction lives in table.cpp.
+// driver, the memory-study sweep and the landscape metrics.  The dispatch-table construction
+// lives in table.cpp.
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
