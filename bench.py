@@ -503,6 +503,66 @@ def run_memory(args, sg, torch, ctx, stream):
     return res
 
 
+def run_concurrent(args, sg, torch, ctx, stream):
+    """Concurrent execution of split plans (the first step towards a concurrent-split cost model):
+    on the landscape's dispatch table, every cell whose plan splits along M or N is timed with its
+    pieces one after another -- as a sum of kernel times (the DP's cost model) and between two
+    stream markers -- and with its pieces at the same time on the context's streams, between the
+    same two markers.  The two marker-timed figures compare like for like."""
+    step, n = args.step, args.n
+    sizes = np.arange(1, n + 1) * step
+    pool = int(sizes[-1]) ** 2
+    A = torch.empty(pool, dtype=torch.bfloat16, device="cuda")
+    B = torch.empty(pool, dtype=torch.bfloat16, device="cuda")
+    C = torch.empty(pool, dtype=torch.bfloat16, device="cuda")
+    sg.fill_bf16(A, args.seed, 0)
+    sg.fill_bf16(B, args.seed, 1)
+    torch.cuda.synchronize()
+    variants = [int(v) for v in args.variants.split(",")]
+    t0 = time.perf_counter()
+    if args.table:
+        table = sg.Table.load(args.table)
+    else:
+        table = ctx.build_table(step, n, n, n, variants, A, B, C, c_dtype=sg.BF16, warmup=args.shape_warmup,
+                                reps=args.reps, order_seed=args.order_seed, stream=stream)
+    table_s = time.perf_counter() - t0
+    ctx.set_table(table)
+    cells = [(int(m), int(nn), int(k)) for m in sizes for nn in sizes for k in sizes]
+    split = [c for c in cells if table.lookup(*c)["action"] in (sg.ACT_SPLIT_M, sg.ACT_SPLIT_N)]
+    order = np.random.default_rng(args.order_seed).permutation(len(split))
+    shapes = [split[i] for i in order]
+    ksum = np.empty(len(split))     # sequential, sum of kernel times (the table's cost model)
+    seq = np.empty(len(split))      # sequential, between stream markers
+    conc = np.empty(len(split))     # concurrent pieces, between stream markers
+    ksum[order] = ctx.sweep(shapes, A, B, C, mode=sg.MODE_DP, c_dtype=sg.BF16, warmup=args.shape_warmup,
+                            reps=args.reps, stream=stream)
+    try:
+        for mode, out in ((2, seq), (1, conc)):
+            ctx.set_concurrent_splits(mode)
+            out[order] = ctx.sweep(shapes, A, B, C, mode=sg.MODE_DP, c_dtype=sg.BF16,
+                                   warmup=args.shape_warmup, reps=args.reps, stream=stream)
+    finally:
+        ctx.set_concurrent_splits(0)
+    fl = np.array([2.0 * m * nn * k for m, nn, k in split])
+    tf_seq, tf_conc = fl / seq / 1e12, fl / conc / 1e12
+    r = seq / conc
+    leaves = np.array([table.plan_leaves(*c) for c in split])
+    res = {"table_grid": "{%d..%d}^3 step %d" % (step, step * n, step), "table_build_s": table_s,
+           "split_cells": len(split), "frac_of_grid": len(split) / len(cells),
+           "leaves_mean": float(leaves.mean()),
+           "sequential_kernel_sum_mean_tflops": float((fl / ksum / 1e12).mean()),
+           "sequential_mean_tflops": float(tf_seq.mean()), "concurrent_mean_tflops": float(tf_conc.mean()),
+           "speedup_mean": float(r.mean()), "speedup_median": float(np.median(r)),
+           "frac_faster": float((r > 1.0).mean()), "frac_faster_10pct": float((r > 1.1).mean()),
+           "frac_slower_10pct": float((r < 1 / 1.1).mean()),
+           # marker-timed: the landscape mean would gain this much if each split cell ran the
+           # faster of the two executions
+           "landscape_mean_gain_tflops": float(np.sum(np.maximum(tf_conc, tf_seq) - tf_seq) / len(cells))}
+    log("concurrent splits: %d cells, sequential %.1f -> concurrent %.1f TFLOP/s mean, speed-up median %.3f"
+        % (len(split), res["sequential_mean_tflops"], res["concurrent_mean_tflops"], res["speedup_median"]))
+    return res
+
+
 EVIDENCE_SHAPES = [(4096, 4096, 4096), (3840, 2048, 4096), (4096, 4096, 128)]
 EVIDENCE_VARIANTS = [0, 8, 12, 16, 24]   # 256x256, 128x256, 128x128, 128x64, 64x64 (no split)
 
@@ -620,13 +680,14 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--dump", default=None, help="write per-shape arrays (.npz) here")
-    ap.add_argument("--workload", choices=["sweep", "grouped", "serve", "offgrid", "fineN", "decomp", "shapes", "memory"], default="sweep",
+    ap.add_argument("--workload", choices=["sweep", "grouped", "serve", "offgrid", "fineN", "decomp", "shapes", "memory", "concurrent"], default="sweep",
                     help="sweep: the landscape (headline) plus a serving leg; grouped: config 4; "
                          "serve: config 5 at its full duration; offgrid: config 3; fineN: the "
                          "fine-N cross-tile sweep; decomp: the four-surface decomposition of "
                          "every tile kernel with its memory-only twin; shapes: 4096^3, 3840x2048x4096 "
                          "and 4096x4096x128 on several tile kernels (counter evidence); memory: the "
-                         "buffer read/write study (co-allocation, load/store, warm-up, order)")
+                         "buffer read/write study (co-allocation, load/store, warm-up, order); "
+                         "concurrent: the DP's M/N split plans with their pieces run at the same time")
     ap.add_argument("--groups", type=int, default=512)
     ap.add_argument("--serve-rate", type=float, default=2000.0)
     ap.add_argument("--serve-seconds", type=float, default=None,
@@ -685,6 +746,15 @@ def main():
             config={"workload": "fine-N sweep: M = K = 4096, N = 32..4096 step 32, BF16 NN, BF16 out, "
                                 "every tile of the variant set and their best-of envelope"},
             fine_n=res, **common)), flush=True)
+        return
+    if args.workload == "concurrent":
+        res = run_concurrent(args, sg, torch, ctx, stream)
+        print(json.dumps(dict(
+            metric="split plans: median speed-up of concurrent over sequential pieces",
+            value=res["speedup_median"], unit="ratio", higher_is_better=True, ms_per_step=None,
+            config={"workload": "every M/N-split cell of the {%d..%d}^3 step %d dispatch table, BF16 NN, "
+                                "BF16 out" % (args.step, args.step * args.n, args.step)},
+            concurrent=res, **common)), flush=True)
         return
     if args.workload == "memory":
         res = run_memory(args, sg, torch, ctx, stream)

@@ -69,6 +69,17 @@ int sg_ctx_set_plain_variant(sg_ctx* ctx, int variant);
 /* every > 0: sweeps and table measurements print one progress line to stderr every `every`
  * shapes; 0 (default) keeps them silent. */
 int sg_ctx_set_progress(sg_ctx* ctx, int every);
+/* Concurrent split plans: on = 1 runs the pieces of a dispatch-table plan that has no K pieces
+ * (its M and N pieces write disjoint parts of C) at the same time, on up to four streams the
+ * context owns (default priority), forked from and joined back into the caller's stream, each
+ * piece in its own slice of the workspace; sg_sweep then times such a run between two markers
+ * on the caller's stream (the fork and a marker after the joins, so fork / join latency is
+ * included) and leaves it out of the per-variant kernel accounting.  Plans with K pieces stay
+ * sequential.  on = 2 runs such plans one after another on the caller's stream but times them
+ * between the same two markers (the like-for-like reference for on = 1).
+ * Default 0: pieces run one after another on the caller's stream, as the paper executes them,
+ * and a run's time is the sum of its kernels' times. */
+int sg_ctx_set_concurrent_splits(sg_ctx* ctx, int on);
 /* Reserve at least `bytes` of workspace now, so later calls do not allocate. */
 int sg_ctx_reserve_workspace(sg_ctx* ctx, size_t bytes);
 

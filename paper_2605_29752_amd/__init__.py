@@ -110,6 +110,7 @@ _SIGS = {
     "sg_table_load": (_i32, [ctypes.c_char_p, _i32, ctypes.POINTER(_p)]),
     "sg_fill_bf16": (_i32, [_p, _i64, ctypes.c_uint64, ctypes.c_uint64, _i64, _i32, _d, _p]),
     "sg_mem_read_blocks": (_i64, [_i64]),
+    "sg_ctx_set_concurrent_splits": (_i32, [_p, _i32]),
     "sg_mem_read": (_i32, [_p, _i64, _p, _p]),
     "sg_mem_write": (_i32, [_p, _i64, ctypes.c_uint32, _p]),
     "sg_mem_sweep": (_i32, [_p, _p, _i64, _i32, _i32, _i32, _i32, _i32, _p, _p]),
@@ -410,6 +411,11 @@ class Context:
 
     def set_progress(self, every: int):
         check(lib().sg_ctx_set_progress(self.handle, every))
+
+    def set_concurrent_splits(self, mode):
+        """Pieces of M / N split plans: 0 / False one after another (kernel-time sum), 1 / True
+        at the same time on the context's streams, 2 one after another timed like 1."""
+        check(lib().sg_ctx_set_concurrent_splits(self.handle, int(mode)))
 
     def reserve_workspace(self, nbytes: int):
         check(lib().sg_ctx_reserve_workspace(self.handle, nbytes))

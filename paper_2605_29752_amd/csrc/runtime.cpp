@@ -36,7 +36,13 @@ struct sg_ctx {
     void* ws = nullptr;
     size_t ws_bytes = 0;
     const sg_table* table = nullptr;
-    std::vector<hipEvent_t> events;
+    std::vector<hipEvent_t> events;   // stamped by kernel dispatches only
+    std::vector<hipEvent_t> marks;    // recorded on streams only (forks, joins, interval ends):
+                                      // an event is never used both ways
+    // concurrent execution of split plans: the pieces of a plan without K pieces go to these
+    // streams (default priority), forked from and joined back into the caller's stream
+    int concurrent_splits = 0;    // 0 off, 1 concurrent, 2 sequential timed like 1
+    std::vector<hipStream_t> aux;
     // accounting of the most recent sweep (timed runs only)
     std::vector<int64_t> acct_launches;
     std::vector<double> acct_seconds;
@@ -56,6 +62,24 @@ struct DeviceGuard {
         if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
     }
 };
+
+int ensure_events(sg_ctx* ctx, size_t n) {
+    while (ctx->events.size() < n) {
+        hipEvent_t e;
+        SG_HIP(hipEventCreate(&e));
+        ctx->events.push_back(e);
+    }
+    return SG_OK;
+}
+
+int ensure_marks(sg_ctx* ctx, size_t n) {
+    while (ctx->marks.size() < n) {
+        hipEvent_t e;
+        SG_HIP(hipEventCreate(&e));
+        ctx->marks.push_back(e);
+    }
+    return SG_OK;
+}
 
 int ensure_ws(sg_ctx* ctx, size_t bytes) {
     if (bytes <= ctx->ws_bytes) return SG_OK;
@@ -185,6 +209,31 @@ size_t plan_workspace(const Problem& pr, const std::vector<Leaf>& leaves, size_t
     return acc + part;
 }
 
+// A plan whose leaves may run at the same time: two or more leaves, none of them a K piece
+// (K pieces accumulate into one output region; M and N pieces write disjoint regions).
+bool plan_is_concurrent(const std::vector<Leaf>& leaves) {
+    if (leaves.size() < 2) return false;
+    for (const Leaf& L : leaves)
+        if (!(L.first && L.last)) return false;
+    return true;
+}
+
+// Workspace of a concurrent plan: one slice per leaf (split-K partials, packed operands), so
+// leaves in flight together never share scratch.  offs[i] = byte offset of leaf i's slice.
+size_t plan_workspace_concurrent(const Problem& pr, const std::vector<Leaf>& leaves, std::vector<size_t>& offs) {
+    size_t total = 0;
+    offs.clear();
+    for (const Leaf& L : leaves) {
+        LaunchDesc d{};
+        d.M = L.m; d.N = L.n; d.K = L.k; d.Ml = L.Ml; d.Nl = L.Nl; d.Kl = L.Kl;
+        d.A = pr.A + L.m0 * pr.lda + L.k0; d.lda = pr.lda;
+        d.B = pr.B + L.k0 * pr.ldb + L.n0; d.ldb = pr.ldb;
+        offs.push_back(total);
+        total += (launch_workspace_bytes(L.variant, d) + 255) & ~size_t(255);
+    }
+    return total;
+}
+
 // Enqueue one leaf.  Output routing (C FP32: accumulate in place; C BF16 with a K split:
 // accumulate in the FP32 plan accumulator W and round once in the last piece).
 int run_leaf(const Problem& pr, const Leaf& L, void* ws, size_t acc_bytes, hipStream_t s,
@@ -251,6 +300,38 @@ int validate(const sg_gemm_args* a) {
     return SG_OK;
 }
 
+constexpr size_t kMaxAux = 4;   // streams for the pieces of one concurrent plan
+
+int ensure_aux(sg_ctx* ctx, size_t n) {
+    while (ctx->aux.size() < n) {
+        hipStream_t st;
+        SG_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));   // default priority
+        ctx->aux.push_back(st);
+    }
+    return SG_OK;
+}
+
+// Enqueue a concurrent plan: `fork` is recorded on s and every auxiliary stream waits for it;
+// leaf i runs on stream i % n in its own workspace slice offs[i]; each stream then records
+// joins[j] and s waits for all of them.
+int run_concurrent(sg_ctx* ctx, const Problem& pr, const std::vector<Leaf>& leaves,
+                   const std::vector<size_t>& offs, hipStream_t s, hipEvent_t fork, const hipEvent_t* joins) {
+    const size_t ns = std::min(leaves.size(), kMaxAux);
+    int rc = ensure_aux(ctx, ns);
+    if (rc) return rc;
+    SG_HIP(hipEventRecord(fork, s));
+    for (size_t j = 0; j < ns; ++j) SG_HIP(hipStreamWaitEvent(ctx->aux[j], fork, 0));
+    for (size_t i = 0; i < leaves.size(); ++i) {
+        rc = run_leaf(pr, leaves[i], ctx->ws, offs[i], ctx->aux[i % ns]);
+        if (rc) return rc;
+    }
+    for (size_t j = 0; j < ns; ++j) {
+        SG_HIP(hipEventRecord(joins[j], ctx->aux[j]));
+        SG_HIP(hipStreamWaitEvent(s, joins[j], 0));
+    }
+    return SG_OK;
+}
+
 int gemm_impl(sg_ctx* ctx, const sg_gemm_args* a, hipStream_t s, std::vector<Leaf>* keep = nullptr) {
     int rc = validate(a);
     if (rc) return rc;
@@ -273,6 +354,14 @@ int gemm_impl(sg_ctx* ctx, const sg_gemm_args* a, hipStream_t s, std::vector<Lea
     std::vector<Leaf>& leaves = keep ? *keep : local;
     rc = make_plan(ctx, pr, a->mode, a->variant, leaves);
     if (rc) return rc;
+    if (ctx->concurrent_splits == 1 && plan_is_concurrent(leaves)) {
+        std::vector<size_t> offs;
+        rc = ensure_ws(ctx, plan_workspace_concurrent(pr, leaves, offs));
+        if (rc) return rc;
+        rc = ensure_marks(ctx, 1 + kMaxAux);
+        if (rc) return rc;
+        return run_concurrent(ctx, pr, leaves, offs, s, ctx->marks[0], &ctx->marks[1]);
+    }
     size_t acc_bytes = 0;
     size_t need = plan_workspace(pr, leaves, &acc_bytes);
     rc = ensure_ws(ctx, need);
@@ -317,7 +406,12 @@ int sg_ctx_create(int device, sg_ctx** out) {
 int sg_ctx_destroy(sg_ctx* ctx) {
     if (!ctx) return SG_OK;
     DeviceGuard guard(ctx->device);
+    for (hipStream_t st : ctx->aux) {
+        (void)hipStreamSynchronize(st);
+        (void)hipStreamDestroy(st);
+    }
     for (hipEvent_t e : ctx->events) (void)hipEventDestroy(e);
+    for (hipEvent_t e : ctx->marks) (void)hipEventDestroy(e);
     if (ctx->ws) {
         (void)hipDeviceSynchronize();
         (void)hipFree(ctx->ws);
@@ -330,6 +424,12 @@ int sg_ctx_set_plain_variant(sg_ctx* ctx, int variant) {
     if (!ctx) return fail(SG_EINVAL, "NULL ctx");
     if (variant < 0 || variant >= kNumVariants) return fail(SG_EINVAL, "variant out of range");
     ctx->plain_variant = variant;
+    return SG_OK;
+}
+
+int sg_ctx_set_concurrent_splits(sg_ctx* ctx, int on) {
+    if (!ctx || on < 0 || on > 2) return fail(SG_EINVAL, "bad argument");
+    ctx->concurrent_splits = on;
     return SG_OK;
 }
 
@@ -465,22 +565,18 @@ int sg_fill_bf16(void* dst, int64_t n, uint64_t seed, uint64_t stream, int64_t o
 // ---- sweep driver ----------------------------------------------------------------------------
 namespace sg {
 
-static int ensure_events(sg_ctx* ctx, size_t n) {
-    while (ctx->events.size() < n) {
-        hipEvent_t e;
-        SG_HIP(hipEventCreate(&e));
-        ctx->events.push_back(e);
-    }
-    return SG_OK;
-}
-
 // Time `reps` runs of the plan `leaves` (after one untimed run).  Every kernel launch carries
 // start/stop events stamped by its own dispatch packet, so a run's time is the sum of its
 // kernels' execution times (host launch gaps excluded).  Returns mean seconds per run; adds
 // per-variant tile-kernel time (a split-K reduction excluded: a third event ends at the tile
 // kernel), launch counts and algorithmic FLOP to the context's accounting.
+int time_plan_concurrent(sg_ctx* ctx, const Problem& pr, const std::vector<Leaf>& leaves, int reps,
+                         hipStream_t s, double* sec, bool account);
+
 int time_plan(sg_ctx* ctx, const Problem& pr, const std::vector<Leaf>& leaves, int reps,
               hipStream_t s, double* sec, bool account) {
+    if (ctx->concurrent_splits != 0 && plan_is_concurrent(leaves))
+        return time_plan_concurrent(ctx, pr, leaves, reps, s, sec, account);
     size_t acc_bytes = 0;
     int rc = ensure_ws(ctx, plan_workspace(pr, leaves, &acc_bytes));
     if (rc) return rc;
@@ -519,6 +615,51 @@ int time_plan(sg_ctx* ctx, const Problem& pr, const std::vector<Leaf>& leaves, i
                 ctx->acct_flops[L.variant] += 2.0 * (double)L.m * (double)L.n * (double)L.k;
             }
         }
+    *sec = total / reps;
+    return SG_OK;
+}
+
+// The same for a plan whose leaves may run together: a run's time is the interval between two
+// markers on the caller's stream, one before the leaves (the fork) and one after them (after
+// the joins), so it includes the launch and fork / join latency that a sum of kernel times does
+// not.  Mode 1 runs the leaves on the auxiliary streams; mode 2 runs them one after another on
+// s, timed the same way, as the like-for-like reference.  These runs are not added to the
+// per-variant kernel accounting.
+int time_plan_concurrent(sg_ctx* ctx, const Problem& pr, const std::vector<Leaf>& leaves, int reps,
+                         hipStream_t s, double* sec, bool /*account*/) {
+    std::vector<size_t> offs;
+    int rc = ensure_ws(ctx, plan_workspace_concurrent(pr, leaves, offs));
+    if (rc) return rc;
+    const size_t ns = std::min(leaves.size(), kMaxAux);
+    const size_t per = 2 + ns;                     // fork, joins, end marker
+    rc = ensure_marks(ctx, per * (size_t)reps);
+    if (rc) return rc;
+    auto run = [&](size_t b) -> int {
+        if (ctx->concurrent_splits == 1) return run_concurrent(ctx, pr, leaves, offs, s, ctx->marks[b], &ctx->marks[b + 1]);
+        SG_HIP(hipEventRecord(ctx->marks[b], s));
+        for (size_t i = 0; i < leaves.size(); ++i) {
+            int e = run_leaf(pr, leaves[i], ctx->ws, offs[i], s);
+            if (e) return e;
+        }
+        return SG_OK;
+    };
+    rc = run(0);                                   // untimed
+    if (rc) return rc;
+    SG_HIP(hipStreamSynchronize(s));
+    for (int r = 0; r < reps; ++r) {
+        const size_t b = per * r;
+        rc = run(b);
+        if (rc) return rc;
+        SG_HIP(hipEventRecord(ctx->marks[b + 1 + ns], s));
+    }
+    SG_HIP(hipStreamSynchronize(s));
+    double total = 0.0;
+    for (int r = 0; r < reps; ++r) {
+        const size_t b = per * r;
+        float ms = 0.f;
+        SG_HIP(hipEventElapsedTime(&ms, ctx->marks[b], ctx->marks[b + 1 + ns]));
+        total += (double)ms * 1e-3;
+    }
     *sec = total / reps;
     return SG_OK;
 }

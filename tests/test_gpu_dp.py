@@ -143,3 +143,57 @@ def test_sweep_driver_and_accounting(ctx):
     assert la[3] == 3 * 4 and la.sum() == 12
     assert fl[3] == pytest.approx(4 * sum(2.0 * m * n * k for m, n, k in shapes))
     assert se[3] == pytest.approx(4 * sec.sum(), rel=0.2)
+
+
+@pytest.mark.parametrize("c_dtype", [F32, BF16])
+def test_concurrent_split_pieces_bit_identical(ctx, c_dtype):
+    """Plans whose M / N pieces run at the same time on the context's streams (each in its own
+    workspace slice, split-K variants among them) give the bits of sequential execution, and
+    are exact on integer inputs; plans with K pieces keep running sequentially.  Grid and
+    off-grid shapes, and a second pass that reuses the streams and events."""
+    step, shape = 64, (5, 5, 5)
+    t, T0 = _random_table(4, shape, step, [3, 6, 10, 25, 27])
+    ctx.set_table(t)
+    rng = np.random.default_rng(9)
+    shapes = [tuple((c + 1) * step for c in cell) for cell in np.ndindex(shape)][::3]
+    shapes += [tuple(int(x) for x in rng.integers(1, 5 * step + 1, 3)) for _ in range(12)]
+    try:
+        for rnd in range(2):
+            for i, (M, N, K) in enumerate(shapes):
+                A, B = inputs(800 + i, M, N, K, "int")
+                seq = run_gemm(ctx, A, B, c_dtype, mode=sg.MODE_DP)
+                ctx.set_concurrent_splits(True)
+                try:
+                    conc = run_gemm(ctx, A, B, c_dtype, mode=sg.MODE_DP)
+                finally:
+                    ctx.set_concurrent_splits(False)
+                assert np.array_equal(seq, conc), ((M, N, K), t.lookup(M, N, K))
+                if rnd == 0:
+                    check_exact(conc, A, B, c_dtype)
+    finally:
+        ctx.set_table(None)
+
+
+def test_concurrent_split_sweep_timing(ctx):
+    """The sweep times a concurrent plan between two markers on the caller's stream: positive
+    and finite for every split cell."""
+    import torch
+    step, shape = 64, (5, 5, 5)
+    t, T0 = _random_table(4, shape, step, [3, 6, 10, 25, 27])
+    ctx.set_table(t)
+    split = [tuple((c + 1) * step for c in cell) for cell in np.ndindex(shape)
+             if t.lookup(*[(c + 1) * step for c in cell])["action"] in (sg.ACT_SPLIT_M, sg.ACT_SPLIT_N)]
+    assert split
+    pool = torch.zeros(512 * 512, dtype=torch.bfloat16, device="cuda")
+    C = torch.zeros(512 * 512, dtype=torch.bfloat16, device="cuda")
+    try:
+        ctx.set_concurrent_splits(2)
+        seq = ctx.sweep(split, pool, pool, C, mode=sg.MODE_DP, warmup=1, reps=3)
+        ctx.set_concurrent_splits(1)
+        conc = ctx.sweep(split, pool, pool, C, mode=sg.MODE_DP, warmup=1, reps=3)
+    finally:
+        ctx.set_concurrent_splits(False)
+        ctx.set_table(None)
+    say("split cells", len(split), "sequential us", seq[:4] * 1e6, "concurrent us", conc[:4] * 1e6)
+    assert np.all(conc > 0) and np.all(np.isfinite(conc))
+    assert np.all(seq > 0) and np.all(np.isfinite(seq))
