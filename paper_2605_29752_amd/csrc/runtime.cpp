@@ -565,6 +565,16 @@ int sg_fill_bf16(void* dst, int64_t n, uint64_t seed, uint64_t stream, int64_t o
 // ---- sweep driver ----------------------------------------------------------------------------
 namespace sg {
 
+// Whether a leaf's launch is followed by a separate split-K reduction (and so stamps its mid
+// event): the splits that are not empty over the leaf's K extent, not the variant's nominal
+// count (a split-K variant on a short K runs as one split).
+bool stamps_mid(const Leaf& L) {
+    int S = 1;
+    int64_t kc = 0;
+    split_geometry(L.variant, L.Kl, &S, &kc);
+    return S > 1;
+}
+
 // Time `reps` runs of the plan `leaves` (after one untimed run).  Every kernel launch carries
 // start/stop events stamped by its own dispatch packet, so a run's time is the sum of its
 // kernels' execution times (host launch gaps excluded).  Returns mean seconds per run; adds
@@ -591,7 +601,7 @@ int time_plan(sg_ctx* ctx, const Problem& pr, const std::vector<Leaf>& leaves, i
     size_t e = 0;
     for (int r = 0; r < reps; ++r)
         for (const Leaf& L : leaves) {
-            const bool split = variant_splits(L.variant) > 1;
+            const bool split = stamps_mid(L);
             rc = run_leaf(pr, L, ctx->ws, acc_bytes, s, ctx->events[e], ctx->events[e + 1],
                           split ? ctx->events[e + 2] : nullptr);
             if (rc) return rc;
@@ -602,7 +612,7 @@ int time_plan(sg_ctx* ctx, const Problem& pr, const std::vector<Leaf>& leaves, i
     e = 0;
     for (int r = 0; r < reps; ++r)
         for (const Leaf& L : leaves) {
-            const bool split = variant_splits(L.variant) > 1;
+            const bool split = stamps_mid(L);
             float ms = 0.f, ms_kernel = 0.f;
             SG_HIP(hipEventElapsedTime(&ms, ctx->events[e], ctx->events[e + 1]));
             if (split) SG_HIP(hipEventElapsedTime(&ms_kernel, ctx->events[e], ctx->events[e + 2]));
