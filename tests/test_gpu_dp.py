@@ -197,3 +197,17 @@ def test_concurrent_split_sweep_timing(ctx):
     say("split cells", len(split), "sequential us", seq[:4] * 1e6, "concurrent us", conc[:4] * 1e6)
     assert np.all(conc > 0) and np.all(np.isfinite(conc))
     assert np.all(seq > 0) and np.all(np.isfinite(seq))
+
+
+def test_sweep_split_variant_on_single_split_k(ctx):
+    """A split-K variant whose K extent fits one split runs without a reduction; the sweep must
+    time it from the tile kernel alone (regression: it asked for the reduction's event)."""
+    import torch
+    pool = torch.zeros(256 * 256, dtype=torch.bfloat16, device="cuda")
+    C = torch.zeros(256 * 256, dtype=torch.bfloat16, device="cuda")
+    for v in (1, 13, 27):                        # 256x256 s2, 128x128 s2, 64x64 s8
+        sec = ctx.sweep([(128, 128, 64), (256, 192, 32), (192, 256, 128)], pool, pool, C,
+                        mode=sg.MODE_VARIANT, variant=v, warmup=1, reps=2)
+        assert np.all(sec > 0) and np.all(np.isfinite(sec))
+        la, se, fl = ctx.kernel_times()
+        assert la[v] == 6 and se[v] > 0
