@@ -567,6 +567,54 @@ def run_concurrent(args, sg, torch, ctx, stream):
     return res
 
 
+def run_vendor(args, sg, torch, ctx, stream):
+    """Context, not this library: the vendor GEMM library (torch.matmul on ROCm) over the same
+    landscape with the same protocol -- randomized order, `shape_warmup` warm-up calls, then per
+    shape one untimed and `reps` timed calls, BF16 in and out.  Each shape's calls are timed
+    here by stream events around the back-to-back calls (host launch gaps included); under a
+    kernel trace the same run gives dispatch durations comparable to the library's sweep (a
+    one-word fill kernel of this library precedes each shape's calls and marks the boundary).
+    The shape order is written to --dump (.vendor_order.npy) when given."""
+    step, n = args.step, args.n
+    sizes = np.arange(1, n + 1) * step
+    pool = int(sizes[-1]) ** 2
+    A = torch.empty(pool, dtype=torch.bfloat16, device="cuda")
+    B = torch.empty(pool, dtype=torch.bfloat16, device="cuda")
+    C = torch.empty(pool, dtype=torch.bfloat16, device="cuda")
+    sg.fill_bf16(A, args.seed, 0)
+    sg.fill_bf16(B, args.seed, 1)
+    torch.cuda.synchronize()
+    grid = [(int(m), int(nn), int(k)) for m in sizes for nn in sizes for k in sizes]
+    order = np.random.default_rng(args.order_seed).permutation(len(grid))
+    sec = np.empty(len(grid))
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def call(M, N, K):
+        torch.matmul(A[:M * K].view(M, K), B[:K * N].view(K, N), out=C[:M * N].view(M, N))
+
+    mark = torch.empty(16, dtype=torch.bfloat16, device="cuda")
+    M, N, K = grid[order[0]]
+    for _ in range(args.shape_warmup):
+        call(M, N, K)
+    for done, i in enumerate(order):
+        M, N, K = grid[i]
+        sg.fill_bf16(mark, 0, 0)          # one tiny kernel of this library: a shape boundary in a trace
+        call(M, N, K)
+        e0.record()
+        for _ in range(args.reps):
+            call(M, N, K)
+        e1.record()
+        e1.synchronize()
+        sec[i] = e0.elapsed_time(e1) * 1e-3 / args.reps
+        if (done + 1) % 4096 == 0:
+            log("vendor %d / %d shapes" % (done + 1, len(grid)))
+    st = stack_stats(sg, sec.reshape(n, n, n), sizes)
+    if args.dump:
+        np.save(args.dump + ".vendor_order.npy", order)
+    return {"grid": "{%d..%d}^3 step %d" % (step, step * n, step), "timing": "stream events",
+            "stack": st}
+
+
 EVIDENCE_SHAPES = [(4096, 4096, 4096), (3840, 2048, 4096), (4096, 4096, 128)]
 EVIDENCE_VARIANTS = [0, 8, 12, 16, 24]   # 256x256, 128x256, 128x128, 128x64, 64x64 (no split)
 
@@ -684,14 +732,15 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--dump", default=None, help="write per-shape arrays (.npz) here")
-    ap.add_argument("--workload", choices=["sweep", "grouped", "serve", "offgrid", "fineN", "decomp", "shapes", "memory", "concurrent"], default="sweep",
+    ap.add_argument("--workload", choices=["sweep", "grouped", "serve", "offgrid", "fineN", "decomp", "shapes", "memory", "concurrent", "vendor"], default="sweep",
                     help="sweep: the landscape (headline) plus a serving leg; grouped: config 4; "
                          "serve: config 5 at its full duration; offgrid: config 3; fineN: the "
                          "fine-N cross-tile sweep; decomp: the four-surface decomposition of "
                          "every tile kernel with its memory-only twin; shapes: 4096^3, 3840x2048x4096 "
                          "and 4096x4096x128 on several tile kernels (counter evidence); memory: the "
                          "buffer read/write study (co-allocation, load/store, warm-up, order); "
-                         "concurrent: the DP's M/N split plans with their pieces run at the same time")
+                         "concurrent: the DP's M/N split plans with their pieces run at the same time; "
+                         "vendor: the vendor GEMM library over the landscape, for context")
     ap.add_argument("--groups", type=int, default=512)
     ap.add_argument("--serve-rate", type=float, default=2000.0)
     ap.add_argument("--serve-seconds", type=float, default=None,
@@ -750,6 +799,15 @@ def main():
             config={"workload": "fine-N sweep: M = K = 4096, N = 32..4096 step 32, BF16 NN, BF16 out, "
                                 "every tile of the variant set and their best-of envelope"},
             fine_n=res, **common)), flush=True)
+        return
+    if args.workload == "vendor":
+        res = run_vendor(args, sg, torch, ctx, stream)
+        print(json.dumps(dict(
+            metric="context: vendor GEMM library (torch.matmul) mean BF16 TFLOPs over the landscape",
+            value=res["stack"]["mean_tflops"], unit="TFLOPs", higher_is_better=True, ms_per_step=None,
+            config={"workload": "BF16 NN GEMM landscape {%d..%d}^3 step %d through torch.matmul, BF16 out"
+                                % (args.step, args.step * args.n, args.step)},
+            vendor=res, **common)), flush=True)
         return
     if args.workload == "concurrent":
         res = run_concurrent(args, sg, torch, ctx, stream)
