@@ -52,6 +52,9 @@ struct DmaTile {
     static constexpr int LDS_BYTES = STAGES * STAGE_BYTES;
     static_assert(A_INSTR >= 1 && B_INSTR >= 1 && B_CHUNKS >= 8, "tile shape");
     static_assert(STAGES >= 2 && STAGES <= 4, "the main loop's waits cover at most two later steps");
+    // A split-K range is a multiple of kBK long and a stage must not run past its end: the
+    // loads check depth against K, not against the split's end.
+    static_assert(kBK % BKD == 0, "a K stage would straddle two split-K ranges");
 };
 
 template <int BM, int BN>
