@@ -30,10 +30,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_BF16_TFLOPS = 2516.6       # MI355X dense BF16 MFMA (256 CUs x 4096 FLOP/clk x 2.4 GHz)
-# The measured variant set (best-of-N's N = 13 of the 28): chosen by greedy forward selection of
-# best-of-set mean TFLOPs over a seeded sample of 1,024 landscape cells with every variant timed
-# (the full 28 reach 476.0 there, these 13 475.8); 256x256 (variant 0) is the plain stack.
-DEFAULT_VARIANTS = "0,4,8,12,13,14,16,20,21,22,24,26,27"
+# The measured variant set (best-of-N's N = 16 of the 32): 13 of tiles 0-6 chosen by greedy
+# forward selection of best-of-set mean TFLOPs over a seeded sample of 1,024 landscape cells with
+# every variant timed (all 28 reached 476.0 there, these 13 475.8), plus the deep-K 64x64 tile
+# without split and with 2 and 4 splits, which win shapes with few tiles (1024^3: 264 against
+# 213; 1024 x 1024 x 4096: 411 against 381).  256x256 (variant 0) is the plain stack.
+DEFAULT_VARIANTS = "0,4,8,12,13,14,16,20,21,22,24,26,27,28,29,30"
 
 
 def log(*a):

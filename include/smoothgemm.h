@@ -106,10 +106,12 @@ typedef struct sg_gemm_args {
 int gemm_bf16_nn_ex(sg_ctx* ctx, const sg_gemm_args* args, void* stream);
 
 /* ---- kernel variants (the tile family) ----------------------------------------------------
- * Variant v: tile BM x BN (256 threads, MFMA 16x16x32 BF16) and a parallel split-K factor S
- * (S > 1: FP32 partials in the workspace, then a fixed-order reduction).  bk is the K
- * granularity of a split (64); lds_bytes is the LDS of the aligned kernel (its ring of 32-deep
- * K stages). */
+ * Variant v = 4 t + log2(S): tile t (BM x BN, 256 threads, MFMA 16x16x32 BF16) and a parallel
+ * split-K factor S in {1, 2, 4, 8} (S > 1: FP32 partials in the workspace, then a fixed-order
+ * reduction).  Tiles 0..7: 256x256, 256x128, 128x256, 128x128, 128x64, 64x128, 64x64, and 64x64
+ * with 128-deep K stages (for shapes with few tiles; per-call only, not in grouped launches).
+ * bk is the K granularity of a split (64; 128 for tile 7), lds_bytes the LDS of the aligned
+ * kernel (its ring of K stages). */
 typedef struct sg_variant_info {
     int id, bm, bn, bk, splits, threads;
     int lds_bytes;
@@ -287,7 +289,8 @@ typedef struct sg_problem {
     void* C;       int64_t ldc;
 } sg_problem;
 typedef struct sg_group_cfg {
-    int tile;       /* tile shape index 0..6: 256x256, 256x128, 128x256, 128x128, 128x64, 64x128, 64x64 */
+    int tile;       /* tile shape index 0..6: 256x256, 256x128, 128x256, 128x128, 128x64, 64x128, 64x64
+                       (tile 7, the deep-K 64x64, is per-call only) */
     int grid_wgs;   /* resident work-groups; 0 = as many as the occupancy allows on every CU */
     int order;      /* 0: longest K first (greedy longest-processing-time), 1: as given */
 } sg_group_cfg;

@@ -35,7 +35,7 @@
 namespace sg {
 
 const TileShape kTiles[kNumTiles] = {{256, 256}, {256, 128}, {128, 256}, {128, 128},
-                                     {128, 64},  {64, 128},  {64, 64}};
+                                     {128, 64},  {64, 128},  {64, 64},   {64, 64}};
 
 // Aligned fast path with direct-to-LDS operand loads (see tile_body_dma.h).
 template <int BM, int BN>
@@ -57,6 +57,36 @@ __global__ __launch_bounds__(256) void sg_gemm_tile_dma_mem(KArgs p) {
     const int m0 = tm * BM, n0 = tn * BN;
     if (m0 >= p.M || n0 >= p.N) return;
     tile_body_dma<BM, BN, true>(p, m0, n0, blockIdx.z, smem);
+}
+
+// The 64 x 64 tile with 128-deep K stages (tile 7), and its memory-only twin.
+template <int BM, int BN>
+__global__ __launch_bounds__(256) void sg_gemm_tile_dma_k128(KArgs p) {
+    __shared__ __attribute__((aligned(1024))) uint16_t smem[dma_smem_bytes<BM, BN, true>() / 2];
+    int tm, tn;
+    tile_coords(p.tiles_m, p.tiles_n, tm, tn);
+    const int m0 = tm * BM, n0 = tn * BN;
+    if (m0 >= p.M || n0 >= p.N) return;
+    tile_body_dma<BM, BN, false, true>(p, m0, n0, blockIdx.z, smem);
+}
+
+template <int BM, int BN>
+__global__ __launch_bounds__(256) void sg_gemm_tile_dma_k128_mem(KArgs p) {
+    __shared__ __attribute__((aligned(1024))) uint16_t smem[dma_smem_bytes<BM, BN, true>() / 2];
+    int tm, tn;
+    tile_coords(p.tiles_m, p.tiles_n, tm, tn);
+    const int m0 = tm * BM, n0 = tn * BN;
+    if (m0 >= p.M || n0 >= p.N) return;
+    tile_body_dma<BM, BN, true, true>(p, m0, n0, blockIdx.z, smem);
+}
+
+typedef void (*TileKernel)(KArgs);
+
+// Direct-to-LDS kernel of a tile and its memory-only twin.
+template <int BM, int BN, bool DEEP>
+static TileKernel dma_kernel(bool twin) {
+    if constexpr (DEEP) return twin ? sg_gemm_tile_dma_k128_mem<BM, BN> : sg_gemm_tile_dma_k128<BM, BN>;
+    else return twin ? sg_gemm_tile_dma_mem<BM, BN> : sg_gemm_tile_dma<BM, BN>;
 }
 
 template <int BM, int BN>
@@ -129,15 +159,17 @@ int lds_bytes_of_tile(int tile) {
         case 3: return dma_smem_bytes<128, 128>();
         case 4: return dma_smem_bytes<128, 64>();
         case 5: return dma_smem_bytes<64, 128>();
-        default: return dma_smem_bytes<64, 64>();
+        case 6: return dma_smem_bytes<64, 64>();
+        default: return dma_smem_bytes<64, 64, true>();
     }
 }
 
 void split_geometry(int variant, int64_t Kl, int* splits, int64_t* k_chunk) {
     const int S = variant_splits(variant);
+    const int64_t g = tile_split_granule(variant_tile(variant));
     int64_t per = (Kl + S - 1) / S;
-    per = (per + kBK - 1) / kBK * kBK;
-    if (per < kBK) per = kBK;
+    per = (per + g - 1) / g * g;
+    if (per < g) per = g;
     *k_chunk = per;
     int64_t s = (Kl + per - 1) / per;
     *splits = (int)(s < 1 ? 1 : s);
@@ -228,17 +260,17 @@ static int launch_pack(const uint16_t* src, int64_t lds, int64_t rows, int64_t c
 // work-groups per CU as its GEMM kernel (the twin needs far fewer registers, which alone would
 // let more of it share a CU and overstate the bandwidth the GEMM's loads can draw).  -1 if the
 // occupancy query fails.
-template <int BM, int BN>
+template <int BM, int BN, bool DEEP>
 static int twin_extra_lds() {
     int occ_gemm = 0, occ_twin = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ_gemm, sg_gemm_tile_dma<BM, BN>, 256, 0) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ_twin, sg_gemm_tile_dma_mem<BM, BN>, 256, 0) != hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ_gemm, dma_kernel<BM, BN, DEEP>(false), 256, 0) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ_twin, dma_kernel<BM, BN, DEEP>(true), 256, 0) != hipSuccess ||
         occ_gemm < 1)
         return -1;
     if (occ_twin <= occ_gemm) return 0;
     const int budget = 160 * 1024 - dma_smem_bytes<BM, BN>();
     for (int extra = 1024; extra <= budget; extra += 1024) {
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ_twin, sg_gemm_tile_dma_mem<BM, BN>, 256,
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ_twin, dma_kernel<BM, BN, DEEP>(true), 256,
                                                          (size_t)extra) != hipSuccess)
             return -1;
         if (occ_twin <= occ_gemm) return extra;
@@ -246,7 +278,7 @@ static int twin_extra_lds() {
     return -1;
 }
 
-template <int BM, int BN>
+template <int BM, int BN, bool DEEP = false>
 static int launch_tile(const LaunchDesc& d, int variant, void* ws, hipStream_t stream) {
     KArgs a;
     a.A = d.A; a.B = d.B;
@@ -309,12 +341,12 @@ static int launch_tile(const LaunchDesc& d, int variant, void* ws, hipStream_t s
         return fail(SG_EINVAL, "memory-only twin: operands the direct-to-LDS path cannot load "
                                "(an extent of 2^31 bytes or more, or no workspace to pack into)");
     if (d.mem_only) {
-        static const int extra = twin_extra_lds<BM, BN>();
+        static const int extra = twin_extra_lds<BM, BN, DEEP>();
         if (extra < 0) { (void)hipGetLastError(); return fail(SG_EHIP, "occupancy query for the memory-only twin failed"); }
-        hipExtLaunchKernelGGL((sg_gemm_tile_dma_mem<BM, BN>), grid, block, (size_t)extra, stream, start, stop1, 0, a);
+        hipExtLaunchKernelGGL(dma_kernel<BM, BN, DEEP>(true), grid, block, (size_t)extra, stream, start, stop1, 0, a);
     }
     else if (aligned)
-        hipExtLaunchKernelGGL((sg_gemm_tile_dma<BM, BN>), grid, block, 0, stream, start, stop1, 0, a);
+        hipExtLaunchKernelGGL(dma_kernel<BM, BN, DEEP>(false), grid, block, 0, stream, start, stop1, 0, a);
     else
         hipExtLaunchKernelGGL((sg_gemm_tile<BM, BN>), grid, block, 0, stream, start, stop1, 0, a);
     SG_HIP(hipGetLastError());
@@ -353,7 +385,8 @@ int launch_variant(int variant, const LaunchDesc& d, void* ws, hipStream_t strea
         case 3: return launch_tile<128, 128>(d, variant, ws, stream);
         case 4: return launch_tile<128, 64>(d, variant, ws, stream);
         case 5: return launch_tile<64, 128>(d, variant, ws, stream);
-        default: return launch_tile<64, 64>(d, variant, ws, stream);
+        case 6: return launch_tile<64, 64>(d, variant, ws, stream);
+        default: return launch_tile<64, 64, true>(d, variant, ws, stream);
     }
 }
 

@@ -216,7 +216,7 @@ int sg_group_plan_create(sg_ctx* ctx, int G, const sg_problem* probs, int c_dtyp
     int rc = validate_problems(G, probs);
     if (rc) return rc;
     if (c_dtype != SG_F32 && c_dtype != SG_BF16) return fail(SG_EINVAL, "bad c_dtype");
-    if (cfg && (cfg->tile < 0 || cfg->tile >= kNumTiles || (cfg->order != 0 && cfg->order != 1) || cfg->grid_wgs < 0))
+    if (cfg && (cfg->tile < 0 || cfg->tile >= kNumGroupTiles || (cfg->order != 0 && cfg->order != 1) || cfg->grid_wgs < 0))
         return fail(SG_EINVAL, "bad group configuration");
     int dev = 0;
     SG_HIP(hipGetDevice(&dev));
@@ -245,7 +245,7 @@ int sg_group_plan_create(sg_ctx* ctx, int G, const sg_problem* probs, int c_dtyp
         SG_HIP(hipEventCreate(&e1));
         double best = INFINITY;
         sg_group_cfg best_cfg{3, 0, 0};
-        for (int t = 0; t < kNumTiles && rc == SG_OK; ++t) {
+        for (int t = 0; t < kNumGroupTiles && rc == SG_OK; ++t) {
             pl->cfg = sg_group_cfg{t, 0, 0};
             rc = plan_upload(pl, probs, s);
             if (rc) break;

@@ -502,11 +502,11 @@ int sg_variant_info_get(int v, sg_variant_info* out) {
     out->id = v;
     out->bm = t.bm;
     out->bn = t.bn;
-    out->bk = kBK;
+    out->bk = tile_split_granule(variant_tile(v));
     out->splits = variant_splits(v);
     out->threads = 256;
     out->lds_bytes = lds_bytes_of_tile(variant_tile(v));
-    std::snprintf(out->name, sizeof out->name, "%dx%dx%d_s%d", t.bm, t.bn, kBK, out->splits);
+    std::snprintf(out->name, sizeof out->name, "%dx%dx%d_s%d", t.bm, t.bn, out->bk, out->splits);
     return SG_OK;
 }
 

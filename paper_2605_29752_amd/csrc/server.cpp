@@ -308,7 +308,7 @@ int sg_server_create(sg_ctx* ctx, const sg_server_cfg* cfg, sg_server** out) {
     *out = nullptr;
     if (cfg->hbm_budget < (1u << 20) || cfg->max_inflight < 1 || cfg->max_inflight > 16 ||
         cfg->max_group < 1 || cfg->max_group > 4096 || cfg->queue_cap < 1 || cfg->n_weights < 1 ||
-        !cfg->weights || cfg->tile < 0 || cfg->tile >= kNumTiles || cfg->max_m < 1 ||
+        !cfg->weights || cfg->tile < 0 || cfg->tile >= kNumGroupTiles || cfg->max_m < 1 ||
         (cfg->mode != SG_SERVE_GROUPED && cfg->mode != SG_SERVE_PER_REQUEST))
         return fail(SG_EINVAL, "bad server configuration");
     int64_t maxK = 0;

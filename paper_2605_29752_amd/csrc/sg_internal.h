@@ -49,16 +49,23 @@ struct LaunchDesc {
 
 enum { ADD_NONE = 0, ADD_F32 = 1, ADD_BF16 = 2 };
 
-constexpr int kNumTiles = 7;
+constexpr int kNumTiles = 8;
 constexpr int kSplitLevels = 4;               // S = 1, 2, 4, 8
 constexpr int kNumVariants = kNumTiles * kSplitLevels;
 constexpr int kBK = 64;
+// Tile 7 is 64 x 64 with 128-deep K stages (tile 6 with 64-deep ones): per call only, the
+// persistent grouped kernel carries tiles 0 .. kNumGroupTiles - 1.
+constexpr int kDeepTile = 7;
+constexpr int kNumGroupTiles = 7;
+constexpr int kDeepBK = 128;
 
 struct TileShape { int bm, bn; };
 extern const TileShape kTiles[kNumTiles];
 
 inline int variant_tile(int v) { return v / kSplitLevels; }
 inline int variant_splits(int v) { return 1 << (v % kSplitLevels); }
+// K granularity of a split (a K stage never straddles two split ranges).
+inline int tile_split_granule(int tile) { return tile == kDeepTile ? kDeepBK : kBK; }
 
 // Number of non-empty K splits and the K extent of each for a launch of K extent Kl.
 void split_geometry(int variant, int64_t Kl, int* splits, int64_t* k_chunk);

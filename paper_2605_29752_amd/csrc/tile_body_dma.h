@@ -26,7 +26,7 @@
 
 namespace sg {
 
-template <int BM, int BN>
+template <int BM, int BN, bool DEEP = false>
 struct DmaTile {
     // Stage depth and ring depth per tile, from measurements (4096^3, TFLOP/s):
     //  * tiles up to 128 x 128: 64-deep stages (two MFMA K steps per barrier) in a two-stage ring;
@@ -35,9 +35,13 @@ struct DmaTile {
     //  * 256 x 128 / 128 x 256: 32-deep stages, two-stage ring: 48 KiB lets two work-groups share
     //    a CU, which hides more latency than deeper prefetch in one (1,070-1,140 against 730
     //    with four stages; 64-deep stages would take 96 KiB and one work-group: 818);
-    //  * 256 x 256: 32-deep stages, four-stage ring (one work-group per CU either way).
+    //  * 256 x 256: 32-deep stages, four-stage ring (one work-group per CU either way);
+    //  * DEEP (the 64 x 64 variant for shapes with few tiles): 128-deep stages, two-stage ring
+    //    (64 KiB: two work-groups per CU instead of five, but the per-stage waits and barrier
+    //    are paid once per four MFMA K steps; 1024^3 212 -> 250, 4096^3 720 -> 570).
+    static_assert(!DEEP || (BM == 64 && BN == 64), "deep stages are for the 64 x 64 tile");
     static constexpr bool SMALL = BM * BN <= 128 * 128;
-    static constexpr int BKD = SMALL ? 64 : 32;          // K per stage
+    static constexpr int BKD = DEEP ? 128 : SMALL ? 64 : 32;   // K per stage
     static constexpr int SUB = BKD / 32;                 // MFMA K steps per stage
     static constexpr int A_CH = BKD / 8;                 // 16-byte chunks per A row
     static constexpr int A_ROWS_PER_INSTR = 512 / BKD;   // 1 KiB = 512 BF16
@@ -54,12 +58,12 @@ struct DmaTile {
     static_assert(STAGES >= 2 && STAGES <= 4, "the main loop's waits cover at most two later steps");
     // A split-K range is a multiple of kBK long and a stage must not run past its end: the
     // loads check depth against K, not against the split's end.
-    static_assert(kBK % BKD == 0, "a K stage would straddle two split-K ranges");
+    static_assert((DEEP ? kDeepBK : kBK) % BKD == 0, "a K stage would straddle two split-K ranges");
 };
 
-template <int BM, int BN>
+template <int BM, int BN, bool DEEP = false>
 constexpr int dma_smem_bytes() {
-    constexpr int ring = DmaTile<BM, BN>::LDS_BYTES;
+    constexpr int ring = DmaTile<BM, BN, DEEP>::LDS_BYTES;
     constexpr int epi = 4 * 16 * (BN / 2 + 4) * 4;
     return ring > epi ? ring : epi;
 }
@@ -115,10 +119,10 @@ __device__ __forceinline__ void dma16(const i32x4_t rsrc, uint32_t voffset, uint
 // same operand loads into the same ring, the same waits and barriers, and the same stores of C,
 // with the fragment reads and the matrix-core products left out (C is written as zeros, plus
 // the addend if one is fused).
-template <int BM, int BN, bool MEM = false>
+template <int BM, int BN, bool MEM = false, bool DEEP = false>
 __device__ __forceinline__ void tile_body_dma(const KArgs& p, const int m0, const int n0, const int kz,
                                               uint16_t* __restrict__ smem) {
-    using T = DmaTile<BM, BN>;
+    using T = DmaTile<BM, BN, DEEP>;
     constexpr int WM = BM / 2, WN = BN / 2;
     constexpr int FM = WM / 16, FN = WN / 16;
     constexpr int PER_STAGE = T::A_INSTR + T::B_INSTR;  // vmcnt units per stage per lane

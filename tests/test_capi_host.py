@@ -39,13 +39,15 @@ def test_library_exports_every_declared_symbol():
 
 def test_variant_family():
     n = sg.num_variants()
-    assert n == 28
+    assert n == 32
     seen = set()
     for v in range(n):
         info = sg.variant_info(v)
         assert info.lds_bytes <= 160 * 1024
-        seen.add((info.bm, info.bn, info.splits))
+        assert info.bk == (128 if v // 4 == 7 else 64) and info.splits == 1 << (v % 4)
+        seen.add((info.bm, info.bn, info.bk, info.splits))
     assert len(seen) == n
+    assert sg.variant_info(28).name == "64x64x128_s1"
     with pytest.raises(sg.SGError):
         sg.variant_info(n)
 

@@ -9,7 +9,7 @@ from gpu_helpers import TOL, check_exact, check_tol, inputs, run_gemm, say
 pytestmark = pytest.mark.gpu
 
 sg = pytest.importorskip("paper_2605_29752_amd")
-NV = 28
+NV = 32
 F32, BF16 = 0, 1
 
 

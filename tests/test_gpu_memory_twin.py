@@ -11,7 +11,7 @@ from gpu_helpers import inputs, say
 pytestmark = pytest.mark.gpu
 
 sg = pytest.importorskip("paper_2605_29752_amd")
-NV = 28
+NV = 32
 F32, BF16 = 0, 1
 
 
@@ -84,13 +84,18 @@ def test_twin_sweep_times(ctx):
     A = torch.zeros(4096 * 4096, dtype=torch.bfloat16, device="cuda")
     B = torch.zeros(4096 * 4096, dtype=torch.bfloat16, device="cuda")
     C = torch.zeros(4096 * 4096, dtype=torch.bfloat16, device="cuda")
-    for v in (0, 12, 24, 25):
-        t_mem = ctx.sweep(shapes, A, B, C, mode=sg.MODE_MEMORY, variant=v, warmup=1, reps=3)
-        t_gemm = ctx.sweep(shapes, A, B, C, mode=sg.MODE_VARIANT, variant=v, warmup=1, reps=3)
+    for v in (0, 12, 24, 25, 28):
+        t_mem = ctx.sweep(shapes, A, B, C, mode=sg.MODE_MEMORY, variant=v, warmup=2, reps=5)
+        t_gemm = ctx.sweep(shapes, A, B, C, mode=sg.MODE_VARIANT, variant=v, warmup=2, reps=5)
         say("variant", v, "memory", t_mem, "gemm", t_gemm)
         assert np.all(np.isfinite(t_mem)) and np.all(t_mem > 0)
-        # the compute-heavy cube: the twin does the GEMM's loads without its matrix work
-        assert t_mem[2] < t_gemm[2]
+        # on the compute-heavy cube the twin (a subset of its GEMM's work) is never much slower:
+        # for the tiles whose load pipeline sets the pace (128x128 and smaller) it runs close to
+        # the GEMM's time, for 256x256 (one work-group per CU, loads well covered) clearly below
+        # it.  Few-microsecond shapes are left out: single runs there vary by tens of percent.
+        assert t_mem[2] < 1.15 * t_gemm[2], (t_mem, t_gemm)
+        if v == 0:
+            assert t_mem[2] < 0.9 * t_gemm[2]
 
 
 def test_twin_errors(ctx):

@@ -98,3 +98,16 @@ def test_no_spills(asm, bm, bn):
     for key in (".vgpr_spill_count", ".sgpr_spill_count"):
         vals = re.findall(re.escape(key) + r":\s+(\d+)", entry[0])
         assert vals == ["0"], (key, vals)
+
+
+def test_deep_k_kernel_codegen(asm):
+    """The 64x64 tile with 128-deep K stages: MFMAs, no accumulator copies, no spills."""
+    name = "_ZN2sg21sg_gemm_tile_dma_k128ILi64ELi64EEEvNS_5KArgsE"
+    body = kernel_body(asm, name)
+    assert re.search(r"v_mfma_f32_16x16x32_bf16", body)
+    assert not _accumulator_copies(body)
+    meta = asm[asm.index("amdhsa.kernels:"):]
+    entry = [e for e in meta.split("\n  - ") if re.search(r"\.name:\s+" + name + r"\s", e)]
+    assert len(entry) == 1
+    for key in (".vgpr_spill_count", ".sgpr_spill_count"):
+        assert re.findall(re.escape(key) + r":\s+(\d+)", entry[0]) == ["0"], key
