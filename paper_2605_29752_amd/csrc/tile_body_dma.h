@@ -38,7 +38,8 @@ struct DmaTile {
     //  * 256 x 256: 32-deep stages, four-stage ring (one work-group per CU either way);
     //  * DEEP (the 64 x 64 variant for shapes with few tiles): 128-deep stages, two-stage ring
     //    (64 KiB: two work-groups per CU instead of five, but the per-stage waits and barrier
-    //    are paid once per four MFMA K steps; 1024^3 212 -> 250, 4096^3 720 -> 570).
+    //    are paid once per four MFMA K steps; against the 64-deep 64 x 64: 1024^3 213 -> 264,
+    //    2048^3 498 -> 551, 4096^3 686 -> 649).
     static_assert(!DEEP || (BM == 64 && BN == 64), "deep stages are for the 64 x 64 tile");
     static constexpr bool SMALL = BM * BN <= 128 * 128;
     static constexpr int BKD = DEEP ? 128 : SMALL ? 64 : 32;   // K per stage
