@@ -281,9 +281,9 @@ def run_finen(args, sg, torch, ctx, stream):
     seen = set()
     for r, v in enumerate(variants):
         vi = sg.variant_info(v)
-        if vi.splits != 1 or (vi.bm, vi.bn) in seen:
+        if vi.splits != 1 or (vi.bm, vi.bn, vi.bk) in seen:
             continue
-        seen.add((vi.bm, vi.bn))
+        seen.add((vi.bm, vi.bn, vi.bk))
         st, tf = line_stats(T0[r:r + 1], [v])
         st.update(sawtooth(tf, Ns, vi.bn))
         st["tile"] = "%dx%d" % (vi.bm, vi.bn)
@@ -344,9 +344,9 @@ def run_decomp(args, sg, torch, ctx, stream):
     seen = set()
     for v in variants:
         vi = sg.variant_info(v)
-        if vi.splits != 1 or (vi.bm, vi.bn) in seen:
+        if vi.splits != 1 or (vi.bm, vi.bn, vi.bk) in seen:
             continue
-        seen.add((vi.bm, vi.bn))
+        seen.add((vi.bm, vi.bn, vi.bk))
         tg = np.empty(len(grid))
         tm = np.empty(len(grid))
         tg[order] = ctx.sweep(shapes, A, B, C, mode=sg.MODE_VARIANT, variant=v, c_dtype=sg.BF16,
