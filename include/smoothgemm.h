@@ -105,6 +105,22 @@ typedef struct sg_gemm_args {
  * A K split with BF16 output accumulates in an FP32 workspace and rounds once. */
 int gemm_bf16_nn_ex(sg_ctx* ctx, const sg_gemm_args* args, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): gemm_bf16_nn_ex with the same arguments, modes and
+ * results (the same plan and kernels, so bit-identical output), but whatever scratch the call
+ * needs (split-K partials, zero-padded copies of unaligned operands, the FP32 accumulator of a
+ * BF16 K-split plan) comes from a fixed device array of sg_noalloc_scratch_bytes() bytes
+ * (256 MiB) that the library holds on each GPU it runs on until the process ends.  The call
+ * makes no hipMalloc / hipFree and no other allocating library call; the context must have been
+ * created beforehand (creation looks up the array's address on its device).  A call whose plan
+ * needs more scratch than that returns SG_ERANGE before enqueueing anything.  Pieces of a plan
+ * always run one after another on `stream` (the context's concurrent-split setting is ignored).
+ * Every call on a GPU shares that GPU's array and leaves its contents behind: calls that may
+ * overlap on one GPU (other streams, other threads, other contexts) race and must be ordered
+ * by the caller.  Nothing in the array needs to start at zero. */
+int gemm_bf16_nn_ex_noalloc(sg_ctx* ctx, const sg_gemm_args* args, void* stream);
+size_t sg_noalloc_scratch_bytes(void);
+
 /* ---- kernel variants (the tile family) ----------------------------------------------------
  * Variant v = 4 t + log2(S): tile t (BM x BN, 256 threads, MFMA 16x16x32 BF16) and a parallel
  * split-K factor S in {1, 2, 4, 8} (S > 1: FP32 partials in the workspace, then a fixed-order

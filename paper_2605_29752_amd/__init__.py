@@ -87,6 +87,8 @@ _SIGS = {
     "sg_ctx_set_table": (_i32, [_p, _p]),
     "gemm_bf16_nn": (_i32, [_i64, _i64, _i64, _p, _p, _p]),
     "gemm_bf16_nn_ex": (_i32, [_p, ctypes.POINTER(sg_gemm_args), _p]),
+    "gemm_bf16_nn_ex_noalloc": (_i32, [_p, ctypes.POINTER(sg_gemm_args), _p]),
+    "sg_noalloc_scratch_bytes": (ctypes.c_size_t, []),
     "sg_num_variants": (_i32, []),
     "sg_variant_info_get": (_i32, [_i32, ctypes.POINTER(sg_variant_info)]),
     "sg_roughness": (_d, [_p, _i64]),
@@ -425,8 +427,10 @@ class Context:
         check(lib().sg_ctx_set_table(self.handle, table.handle if table else None))
 
     def gemm(self, A, B, C, *, beta: int = 0, mode: int = MODE_DEFAULT, variant: int = 0,
-             M=None, N=None, K=None, lda=None, ldb=None, ldc=None, stream=None):
-        """C (FP32 or BF16 torch tensor) = A @ B (+ C if beta): A, B BF16 torch CUDA tensors."""
+             M=None, N=None, K=None, lda=None, ldb=None, ldc=None, stream=None, noalloc=False):
+        """C (FP32 or BF16 torch tensor) = A @ B (+ C if beta): A, B BF16 torch CUDA tensors.
+        noalloc: use the entry point that takes its scratch from the library's fixed device
+        array instead of the context's workspace."""
         import torch
         if A.dtype != torch.bfloat16 or B.dtype != torch.bfloat16:
             raise TypeError("A and B must be bfloat16")
@@ -444,7 +448,8 @@ class Context:
         a.C, a.ldc = C.data_ptr(), (C.stride(0) if ldc is None else ldc)
         a.c_dtype = F32 if C.dtype == torch.float32 else BF16
         a.beta, a.mode, a.variant = beta, mode, variant
-        check(lib().gemm_bf16_nn_ex(self.handle, ctypes.byref(a), _stream_ptr(stream)))
+        fn = lib().gemm_bf16_nn_ex_noalloc if noalloc else lib().gemm_bf16_nn_ex
+        check(fn(self.handle, ctypes.byref(a), _stream_ptr(stream)))
         return C
 
     def mem_sweep(self, shapes, op: int, alloc: int, *, elem_bytes: int = 4, warmup: int = 5,
@@ -622,6 +627,11 @@ def gemm_grouped(ctx: "Context", probs, c_dtype: int = BF16, tile: int = 3, stre
     cfg = sg_group_cfg(tile, 0, 0)
     check(lib().sg_gemm_grouped(ctx.handle, len(probs), arr, c_dtype, ctypes.byref(cfg),
                                 _stream_ptr(stream)))
+
+
+def noalloc_scratch_bytes() -> int:
+    """Size of the fixed device scratch of the no-allocation entry point."""
+    return int(lib().sg_noalloc_scratch_bytes())
 
 
 def gemm_bf16_nn(M: int, N: int, K: int, A, B, C):

@@ -332,7 +332,11 @@ int run_concurrent(sg_ctx* ctx, const Problem& pr, const std::vector<Leaf>& leav
     return SG_OK;
 }
 
-int gemm_impl(sg_ctx* ctx, const sg_gemm_args* a, hipStream_t s, std::vector<Leaf>* keep = nullptr) {
+// One call.  fixed_ws != nullptr: run in that caller-provided scratch of fixed_cap bytes
+// instead of the context's workspace (no allocation, pieces always one after another); a plan
+// that needs more gives SG_ERANGE before anything is enqueued.
+int gemm_impl(sg_ctx* ctx, const sg_gemm_args* a, hipStream_t s, std::vector<Leaf>* keep = nullptr,
+              void* fixed_ws = nullptr, size_t fixed_cap = 0) {
     int rc = validate(a);
     if (rc) return rc;
     if (a->M == 0 || a->N == 0) return SG_OK;
@@ -354,6 +358,18 @@ int gemm_impl(sg_ctx* ctx, const sg_gemm_args* a, hipStream_t s, std::vector<Lea
     std::vector<Leaf>& leaves = keep ? *keep : local;
     rc = make_plan(ctx, pr, a->mode, a->variant, leaves);
     if (rc) return rc;
+    if (fixed_ws) {
+        size_t acc_bytes = 0;
+        const size_t need = plan_workspace(pr, leaves, &acc_bytes);
+        if (need > fixed_cap)
+            return fail(SG_ERANGE, "this call needs " + std::to_string(need) + " bytes of scratch; the "
+                        "no-allocation entry point has " + std::to_string(fixed_cap));
+        for (const Leaf& L : leaves) {
+            rc = run_leaf(pr, L, fixed_ws, acc_bytes, s);
+            if (rc) return rc;
+        }
+        return SG_OK;
+    }
     if (ctx->concurrent_splits == 1 && plan_is_concurrent(leaves)) {
         std::vector<size_t> offs;
         rc = ensure_ws(ctx, plan_workspace_concurrent(pr, leaves, offs));
@@ -375,6 +391,38 @@ int gemm_impl(sg_ctx* ctx, const sg_gemm_args* a, hipStream_t s, std::vector<Lea
 
 std::mutex g_default_mu;
 sg_ctx* g_default[64] = {nullptr};
+
+// ---- fixed device scratch for gemm_bf16_nn_ex_noalloc ----------------------------------------
+// Split-K partials, zero-padded operand copies and the FP32 accumulator of BF16 K-split plans
+// of the no-allocation entry point live here.  Every call writes each byte it later reads (the
+// partial slices, the packed copies and the accumulator's first piece are written whole), so
+// nothing needs clearing between calls.  In host code `scratch` only names the symbol: the
+// device address of each GPU's copy comes from hipGetSymbolAddress, taken once per device when
+// a context is created on it, and only that address is handed to kernels.
+constexpr size_t kScratchBytes = (size_t)256 << 20;
+__device__ __align__(256) char scratch[kScratchBytes];
+
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[64] = {nullptr};
+
+// With `device` current: look up this device's copy of the scratch array (once per device).
+int scratch_init(int device) {
+    if (device < 0 || device >= 64) return fail(SG_EINVAL, "device ordinal too large");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr[device]) return SG_OK;
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    if (!p) return fail(SG_EHIP, "hipGetSymbolAddress(scratch) returned NULL");
+    g_scratch_ptr[device] = p;
+    return SG_OK;
+}
+
+void* scratch_of(int device) {
+    if (device < 0 || device >= 64) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return g_scratch_ptr[device];
+}
 
 }  // namespace
 
@@ -399,6 +447,11 @@ int sg_ctx_create(int device, sg_ctx** out) {
     c->acct_launches.assign(kNumVariants, 0);
     c->acct_seconds.assign(kNumVariants, 0.0);
     c->acct_flops.assign(kNumVariants, 0.0);
+    const int rc = scratch_init(device);     // the device's scratch address, for the no-allocation call
+    if (rc) {
+        delete c;
+        return rc;
+    }
     *out = c;
     return SG_OK;
 }
@@ -477,6 +530,19 @@ int gemm_bf16_nn_ex(sg_ctx* ctx, const sg_gemm_args* args, void* stream) {
     DeviceGuard guard(ctx->device);
     return gemm_impl(ctx, args, (hipStream_t)stream);
 }
+
+int gemm_bf16_nn_ex_noalloc(sg_ctx* ctx, const sg_gemm_args* args, void* stream) {
+    if (!ctx) return fail(SG_EINVAL, "NULL ctx");
+    DeviceGuard guard(ctx->device);
+    void* ws = scratch_of(ctx->device);
+    if (!ws) return fail(SG_EINVAL, "no scratch address for this device (create the context first)");
+    // host-side leaf list kept per thread: it grows only for a plan longer than any before
+    static thread_local std::vector<Leaf> leaves;
+    if (leaves.capacity() < 256) leaves.reserve(256);
+    return gemm_impl(ctx, args, (hipStream_t)stream, &leaves, ws, kScratchBytes);
+}
+
+size_t sg_noalloc_scratch_bytes(void) { return kScratchBytes; }
 
 int sg_gemm_batch(sg_ctx* ctx, int G, const sg_problem* probs, int c_dtype, int mode, int variant,
                   void* stream) {
