@@ -113,14 +113,36 @@ def wave_efficiency(M: int, N: int, tile: int, cores: int) -> float:
     return W / (math.ceil(W / cores) * cores)
 
 
+def channel_utilisation(L: int, elem_bytes: int, channels: int, interleave: int = 256,
+                        tile_row: int = 256) -> float:
+    """Sec. 9.2, memory term: the address space is striped over `channels` channels in blocks of
+    `interleave` bytes, and a kernel moves rows of `tile_row` elements of a tensor whose
+    leading dimension is L elements.  One such row spans w = min(channels, tile_row e /
+    interleave) channels; consecutive rows start s = (L e / interleave) mod channels blocks
+    apart, so their starts hit channels / gcd(s, channels) distinct channels; the fraction of
+    channels the tensor keeps busy is min(channels, w channels / gcd(s, channels)) / channels."""
+    w = min(channels, max(1, (tile_row * elem_bytes) // interleave))
+    s = ((L * elem_bytes) // interleave) % channels
+    return min(channels, w * channels // math.gcd(s, channels)) / channels
+
+
 def optimal_tflops(M: int, N: int, K: int, peak: float, cores: int, bw_gbs: float,
-                   tiles=(256, 128, 64), c_bytes: int = 2) -> float:
+                   tiles=(256, 128, 64), c_bytes: int = 2, channels: int = 0,
+                   interleave: int = 256) -> float:
     """Sec. 9.2: t_opt = min over tiles T of max(t_compute(T), t_memory), with
-    t_compute(T) = 2MNK / (peak wave_efficiency(T)) and t_memory = (2MK + 2KN + c_bytes MN) / BW
-    (the channel-utilisation factors taken as 1: this HBM's address hash is not public).
+    t_compute(T) = 2MNK / (peak wave_efficiency(T)) and t_memory = 2MK / (BW eta_A) +
+    2KN / (BW eta_B) + c_bytes MN / (BW eta_D), the channel utilisations eta of A (leading
+    dimension K), B and D (leading dimension N) from channel_utilisation; channels = 0 takes
+    every eta as 1 (for a memory whose address-to-channel hash is not public).
     Returns 2MNK / t_opt in TFLOP/s (peak in TFLOP/s, BW in GB/s)."""
     flop = 2.0 * M * N * K
-    t_mem = (2.0 * M * K + 2.0 * K * N + float(c_bytes) * M * N) / (bw_gbs * 1e9)
+    if channels > 0:
+        eta_a = channel_utilisation(K, 2, channels, interleave)
+        eta_b = channel_utilisation(N, 2, channels, interleave)
+        eta_d = channel_utilisation(N, c_bytes, channels, interleave)
+    else:
+        eta_a = eta_b = eta_d = 1.0
+    t_mem = (2.0 * M * K / eta_a + 2.0 * K * N / eta_b + float(c_bytes) * M * N / eta_d) / (bw_gbs * 1e9)
     best = math.inf
     for T in tiles:
         t_comp = flop / (peak * 1e12 * wave_efficiency(M, N, T, cores))

@@ -87,10 +87,54 @@ def test_optimal_compute_plateau_is_peak():
     assert metrics.optimal_tflops(4096, 4096, 4096, **MI355X) == pytest.approx(2516.6)
 
 
-def test_optimal_memory_bound_corner():
-    M, N, K = 4096, 4096, 1
-    t_mem = (2 * M * K + 2 * K * N + 2 * M * N) / 8000e9
-    assert metrics.optimal_tflops(M, N, K, **MI355X) == pytest.approx(2 * M * N * K / t_mem / 1e12)
+def test_optimal_memory_bound_corner_counts_the_tensors_bytes():
+    # a memory-bound shape (K = 1): the optimal moves every byte of the actual tensors once at
+    # the bandwidth; the bytes are counted from arrays of the operand and result types
+    for (M, N, K), c_dtype in [((4096, 4096, 1), np.uint16), ((512, 3000, 2), np.float32)]:
+        A = np.zeros((M, K), dtype=np.uint16)          # BF16 storage
+        B = np.zeros((K, N), dtype=np.uint16)
+        C = np.zeros((M, N), dtype=c_dtype)
+        nbytes = A.nbytes + B.nbytes + C.nbytes
+        got = metrics.optimal_tflops(M, N, K, c_bytes=C.itemsize, **MI355X)
+        assert got * 1e12 * (nbytes / 8000e9) == pytest.approx(2.0 * M * N * K, rel=1e-12)
+
+
+def _channels_touched(L, elem_bytes, channels, interleave, tile_row, rows):
+    """Brute force: walk the rows of a tensor with leading dimension L, list every interleave
+    block each tile row touches, and count the distinct channels (block number mod channels)."""
+    seen = set()
+    for r in range(rows):
+        start = r * L * elem_bytes
+        for byte in range(start, start + tile_row * elem_bytes, interleave):
+            seen.add((byte // interleave) % channels)
+    return len(seen) / channels
+
+
+@pytest.mark.parametrize("channels", [6, 8, 12])
+@pytest.mark.parametrize("elem_bytes", [2, 4])
+def test_channel_utilisation_equals_simulated_striping(channels, elem_bytes):
+    for L in range(128, 4097, 128):
+        want = _channels_touched(L, elem_bytes, channels, 256, 256, rows=4 * channels)
+        assert metrics.channel_utilisation(L, elem_bytes, channels, 256) == pytest.approx(want), (L, elem_bytes)
+
+
+def test_channel_dip_printed_for_b_at_multiples_of_768():
+    # Sec. 9.2: with 6 channels at 256 B, B's utilisation drops to 1/3 whenever N is a multiple
+    # of 768 (and only then, for BF16 rows on the 128-step grid)
+    for N in range(128, 8193, 128):
+        eta = metrics.channel_utilisation(N, 2, 6, 256)
+        assert (eta == pytest.approx(1 / 3)) == (N % 768 == 0), N
+
+
+def test_channel_term_only_lowers_the_memory_roofline():
+    # the channel shares are at most 1: adding them never raises the optimal, and it leaves
+    # compute-bound shapes (far above the ridge) unchanged
+    b580 = dict(peak=108.2, cores=20, bw_gbs=451.0, c_bytes=4)
+    for M, N, K in [(128, 768, 128), (256, 1536, 4096), (3840, 3840, 4096), (128, 128, 128)]:
+        with_ch = metrics.optimal_tflops(M, N, K, channels=6, **b580)
+        without = metrics.optimal_tflops(M, N, K, **b580)
+        assert with_ch <= without + 1e-12
+    assert metrics.optimal_tflops(3840, 3840, 4096, channels=6, **b580) == pytest.approx(108.2)
 
 
 def test_optimal_picks_the_best_filling_tile():
