@@ -38,8 +38,38 @@ PEAK_BF16_TFLOPS = 2516.6       # MI355X dense BF16 MFMA (256 CUs x 4096 FLOP/cl
 DEFAULT_VARIANTS = "0,4,8,12,13,14,16,20,21,22,24,26,27,28,29,30"
 
 
+T_START = time.perf_counter()
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def elapsed() -> float:
+    """Seconds since the benchmark process started."""
+    return time.perf_counter() - T_START
+
+
+def ramp_texture(tf):
+    """Split the roughness of an (M, N, K) TFLOPs landscape into its ramp and its texture, per
+    axis and as the 3-D mean.  Along one line T_0 .. T_{n-1}, sum |T_{i+1} - T_i| is at least
+    |T_{n-1} - T_0|, with equality exactly when the line is monotone: the ramp part
+    |T_{n-1} - T_0| / (n - 1) is the roughness of the smoothest line with those end points (the
+    paper's unavoidable wave-fill ramp is of this kind), and the texture -- roughness minus
+    ramp -- is what the line's ups and downs add to it, the part tile selection and the DP can
+    remove.  Both are averaged over lines like the roughness."""
+    tf = np.asarray(tf, dtype=np.float64)
+    out = {}
+    for name, axis in (("m", 0), ("n", 1), ("k", 2)):
+        t = np.moveaxis(tf, axis, -1)
+        n = t.shape[-1]
+        rough = np.abs(np.diff(t, axis=-1)).sum(axis=-1) / (n - 1)
+        ramp = np.abs(t[..., -1] - t[..., 0]) / (n - 1)
+        out["ramp_" + name] = float(ramp.mean())
+        out["texture_" + name] = float((rough - ramp).mean())
+    out["ramp_3d"] = (out["ramp_m"] + out["ramp_n"] + out["ramp_k"]) / 3.0
+    out["texture_3d"] = (out["texture_m"] + out["texture_n"] + out["texture_k"]) / 3.0
+    return out
 
 
 def stack_stats(sg, sec, sizes):
@@ -51,9 +81,11 @@ def stack_stats(sg, sec, sizes):
     st = sg.landscape_stats(tf)
     sl = tf[:, :, -1]
     slice_rough = float(np.mean([sg.roughness(row) for row in sl]))
+    rt = ramp_texture(tf)
     return {"mean_tflops": st["mean"], "peak_tflops": st["peak"],
             "roughness_3d": st["roughness_3d"], "roughness_n": st["roughness_n"],
             "roughness_m": st["roughness_m"], "roughness_k": st["roughness_k"],
+            "ramp_3d": rt["ramp_3d"], "texture_3d": rt["texture_3d"],
             "slice_k%d_mean" % int(sizes[-1]): float(sl.mean()),
             "slice_k%d_roughness_n" % int(sizes[-1]): slice_rough,
             "frac_of_peak_mean": st["mean"] / PEAK_BF16_TFLOPS,
@@ -84,6 +116,15 @@ def first_principles(sg, stack_secs, sizes, step, n):
     return out
 
 
+def kernel_name(sg, v: int) -> str:
+    """Name of the direct-to-LDS tile kernel that variant v launches on aligned operands (as a
+    profiler lists it)."""
+    vi = sg.variant_info(v)
+    if vi.bk == 128:
+        return "sg_gemm_tile_dma_k128<%d, %d>" % (vi.bm, vi.bn)
+    return "sg_gemm_tile_dma<%d, %d>" % (vi.bm, vi.bn)
+
+
 def kernel_source_hash() -> str:
     """SHA-1 of the tile kernels' source with comments and whitespace removed, so that only a
     change of the code itself retires recorded counter figures."""
@@ -110,45 +151,87 @@ def traffic_bytes(kernel: str):
     return t["hbm_bytes_per_launch"]
 
 
-def cpu_baseline(seconds_budget: float, seed: int):
-    """The FP64 oracle, untuned, on a bounded seeded sample of the grid's smaller shapes."""
+def _cpu_worker(job):
+    """One worker of the CPU baseline: the FP64 oracle on its shapes until the deadline."""
     import oracle
     import synth
+    shapes, seed, deadline = job
+    a_pool = synth.uniform_bf16(seed, synth.STREAM_A, 1, 4096 * 4096).ravel()
+    b_pool = synth.uniform_bf16(seed, synth.STREAM_B, 1, 4096 * 4096).ravel()
+    done = []
+    for (m, n, k) in shapes:
+        if time.time() > deadline and done:
+            break
+        t0 = time.perf_counter()
+        oracle.gemm_f64(a_pool[:m * k].reshape(m, k), b_pool[:k * n].reshape(k, n), want_d=False)
+        done.append((m, n, k, time.perf_counter() - t0))
+    return done
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(seconds_budget: float, seed: int):
+    """The FP64 oracle, untuned (a plain single-threaded loop), run in one process per host core
+    (at most 16) on a bounded seeded sample of the landscape: one process takes the K = 4096,
+    M = 4096 slice's smallest shape (4096 x 128 x 4096), the others seeded grid shapes with
+    M N K <= 2^25, until the time budget.  value = total FLOP / wall time."""
+    import multiprocessing as mp
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    cores = max(1, min(cores, 16))
     rng = np.random.default_rng(seed)
     sizes = np.arange(128, 4097, 128)
-    # operands are the same pool views the GPU uses (first M*K / K*N elements of the pools)
-    cand = [(m, n, k) for m in sizes for n in sizes for k in sizes if m * n * k <= (1 << 25)]
+    cand = [(int(m), int(n), int(k)) for m in sizes for n in sizes for k in sizes if m * n * k <= (1 << 25)]
     order = rng.permutation(len(cand))
-    shapes, flops, secs = [], [], []
-    t_start = time.perf_counter()
-    a_pool = synth.uniform_bf16(seed, synth.STREAM_A, 1, 1 << 20).ravel()
-    b_pool = synth.uniform_bf16(seed, synth.STREAM_B, 1, 1 << 20).ravel()
-    for idx in order:
-        m, n, k = (int(x) for x in cand[idx])
-        A = a_pool[:m * k].reshape(m, k)
-        B = b_pool[:k * n].reshape(k, n)
-        t0 = time.perf_counter()
-        oracle.gemm_f64(A, B, want_d=False)
-        dt = time.perf_counter() - t0
-        shapes.append((m, n, k))
-        flops.append(2.0 * m * n * k)
-        secs.append(dt)
-        if time.perf_counter() - t_start > seconds_budget:
-            break
-    tf = np.array(flops) / np.array(secs) / 1e12
-    return {"value": float(tf.mean()), "unit": "TFLOPs", "cores": 1, "kind": "oracle",
-            "sample": "%d seeded grid shapes with M*N*K <= 2^25 (e.g. %s), plain FP64 C loop, "
-                      "1 thread, %.1f s total; value = mean over the sample of 2MNK/t"
-                      % (len(shapes), "x".join(map(str, shapes[0])), float(np.sum(secs))),
-            "aggregate_tflops": float(np.sum(flops) / np.sum(secs) / 1e12)}
+    lists = [[] for _ in range(cores)]
+    lists[0].append((4096, 128, 4096))
+    for t, idx in enumerate(order):
+        lists[(t % (cores - 1)) + 1 if cores > 1 else 0].append(cand[idx])
+    t_start = time.time()
+    deadline = t_start + seconds_budget
+    with mp.get_context("fork").Pool(cores) as pool:
+        parts = pool.map(_cpu_worker, [(l, seed, deadline) for l in lists])
+    wall = time.time() - t_start
+    done = [d for p in parts for d in p]
+    flops = sum(2.0 * m * n * k for m, n, k, _ in done)
+    per_shape = [2.0 * m * n * k / t / 1e12 for m, n, k, t in done]
+    slice_done = [d for d in parts[0] if d[:3] == (4096, 128, 4096)]
+    return {"value": flops / wall / 1e12, "unit": "TFLOPs", "cores": cores, "kind": "oracle",
+            "cpu_model": cpu_model(), "os_cpu_count": os.cpu_count(),
+            "sample": "%d shapes (4096x128x4096 from the K = 4096, M = 4096 slice, plus seeded grid shapes "
+                      "with M*N*K <= 2^25), plain FP64 C loop, one process per core on %d cores, %.1f s wall; "
+                      "value = total FLOP / wall time" % (len(done), cores, wall),
+            "per_core_mean_tflops": float(np.mean(per_shape)) if per_shape else None,
+            "slice_shape_seconds": slice_done[0][3] if slice_done else None}
 
 
-def run_grouped(args, sg, torch, ctx, stream):
+def percentile(x, q: float) -> float:
+    """Nearest-rank percentile (q in (0, 1]) of a sample."""
+    v = np.sort(np.asarray(x, dtype=np.float64))
+    k = min(max(int(np.ceil(q * v.size)), 1), v.size)
+    return float(v[k - 1])
+
+
+def run_grouped(args, sg, torch, ctx, stream, reps=None):
     """Config 4: 512 groups x 64 GEMMs, log-uniform dims in [64, 4096] rounded to multiples of 8;
-    one autotuned persistent grouped launch per group, all 512 captured in one hipGraph, versus
-    the same problems as 64 separate per-call launches per group."""
+    one persistent grouped launch per group with an autotuned schedule (tile, grid, queue
+    order), all 512 captured in one hipGraph, against the same problems as 64 separate per-call
+    launches per group: best-of-N (the table's per-shape best variant) and the DP plans when the
+    context holds a table, else the group's own tile.  Latency per group: each group's launch
+    (grouped) or its 64 calls (per call) bracketed by events on the stream."""
     rng = np.random.default_rng(4)
     G, NG = 64, args.groups
+    reps = args.steps if reps is None else reps
 
     def dim():
         return int(np.clip(8 * np.round(np.exp(rng.uniform(np.log(64), np.log(4096))) / 8), 64, 4096))
@@ -169,45 +252,81 @@ def run_grouped(args, sg, torch, ctx, stream):
             probs.append((M, N, K, A.data_ptr() + 2 * oa, K, B.data_ptr() + 2 * ob, N, Cs[j].data_ptr(), N))
             flops += 2.0 * M * N * K
         groups.append(probs)
+    gflops = np.array([sum(2.0 * p[0] * p[1] * p[2] for p in pr) for pr in groups])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     plans = [sg.GroupPlan(ctx, pr, sg.BF16, stream=stream) for pr in groups]
     tune_s = time.perf_counter() - t0
-    tiles = [p.info()["tile"] for p in plans]
-    log("grouped: autotuned %d groups in %.1f s; tiles %s" % (NG, tune_s, np.bincount(tiles, minlength=7).tolist()))
+    infos = [p.info() for p in plans]
+    tiles = [i["tile"] for i in infos]
+    cfgs = {}
+    for i in infos:
+        key = "%s grid %d order %s" % (sg.variant_info(4 * i["tile"]).name[:-6], i["grid_wgs"],
+                                       "lpt" if i["order"] == 0 else "given")
+        cfgs[key] = cfgs.get(key, 0) + 1
+    res = {"groups": NG, "problems_per_group": G, "flops": flops, "autotune_s": tune_s,
+           "tile_histogram": np.bincount(tiles, minlength=7).tolist(), "schedules": cfgs}
+    if ctx._table is not None:
+        # the schedules were recorded in the table: planning the same groups again is a lookup
+        t0 = time.perf_counter()
+        again = [sg.GroupPlan(ctx, pr, sg.BF16, stream=stream) for pr in groups]
+        res["replan_from_table_s"] = time.perf_counter() - t0
+        res["table_group_schedules"] = ctx._table.group_schedules()
+        for p in again:
+            p.close()
+    log("grouped: autotuned %d groups in %.1f s; tiles %s" % (NG, tune_s, res["tile_histogram"]))
     graph = sg.Graph(plans, stream)
 
-    def timed(fn, reps):
+    def timed(fn, n):
         fn()
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        best = []
-        for _ in range(reps):
+        ts = []
+        for _ in range(n):
             e0.record(stream)
             fn()
             e1.record(stream)
             e1.synchronize()
-            best.append(e0.elapsed_time(e1) * 1e-3)
-        return float(np.mean(best))
+            ts.append(e0.elapsed_time(e1) * 1e-3)
+        return float(np.mean(ts))
 
-    t_graph = timed(lambda: graph.launch(stream), args.steps)
-    t_plans = timed(lambda: [p.launch(stream) for p in plans], args.steps)
+    def per_group(launch):
+        """Seconds of each group, launched one after another, each between two events."""
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(NG)]
+        for gi in range(NG):
+            ev[gi][0].record(stream)
+            launch(gi)
+            ev[gi][1].record(stream)
+        torch.cuda.synchronize()
+        return np.array([a.elapsed_time(b) * 1e-3 for a, b in ev])
+
     arrs = [sg._problems(pr) for pr in groups]
-    t_call_same = timed(lambda: [sg.gemm_batch(ctx, pr, sg.BF16, sg.MODE_VARIANT, 4 * t, stream, _arr=a)
-                                 for pr, t, a in zip(groups, tiles, arrs)], args.steps)
-    res = {"graph_tflops": flops / t_graph / 1e12, "grouped_no_graph_tflops": flops / t_plans / 1e12,
-           "percall_same_tile_tflops": flops / t_call_same / 1e12,
-           "graph_s": t_graph, "percall_same_tile_s": t_call_same, "flops": flops,
-           "groups": NG, "problems_per_group": G, "autotune_s": tune_s,
-           "tile_histogram": np.bincount(tiles, minlength=7).tolist()}
+    t_graph = timed(lambda: graph.launch(stream), reps)
+    t_plans = timed(lambda: [p.launch(stream) for p in plans], reps)
+    lat_g = per_group(lambda gi: plans[gi].launch(stream))
+    res.update({"graph_tflops": flops / t_graph / 1e12, "grouped_no_graph_tflops": flops / t_plans / 1e12,
+                "graph_s": t_graph,
+                "grouped_latency_ms": {"p50": percentile(lat_g, 0.5) * 1e3, "p99": percentile(lat_g, 0.99) * 1e3,
+                                       "mean": float(lat_g.mean()) * 1e3}})
+    base = [("same_tile", sg.MODE_VARIANT, None)]
     if ctx._table is not None:
-        t_call_best = timed(lambda: [sg.gemm_batch(ctx, pr, sg.BF16, sg.MODE_BEST, 0, stream, _arr=a)
-                                     for pr, a in zip(groups, arrs)], args.steps)
-        res["percall_best_of_n_tflops"] = flops / t_call_best / 1e12
-    res["speedup_vs_percall_same_tile"] = t_call_same / t_graph
+        base = [("best_of_n", sg.MODE_BEST, 0), ("dp", sg.MODE_DP, 0)] + base
+    for name, mode, var in base:
+        vs = [4 * t for t in tiles] if var is None else [var] * NG
+        n_rep = max(2, min(reps, 3))
+        t_call = timed(lambda: [sg.gemm_batch(ctx, pr, sg.BF16, mode, v, stream, _arr=a)
+                                for pr, v, a in zip(groups, vs, arrs)], n_rep)
+        lat_c = per_group(lambda gi: sg.gemm_batch(ctx, groups[gi], sg.BF16, mode, vs[gi], stream, _arr=arrs[gi]))
+        res["percall_%s_tflops" % name] = flops / t_call / 1e12
+        res["percall_%s_latency_ms" % name] = {"p50": percentile(lat_c, 0.5) * 1e3,
+                                               "p99": percentile(lat_c, 0.99) * 1e3,
+                                               "mean": float(lat_c.mean()) * 1e3}
+        res["speedup_vs_percall_%s" % name] = t_call / t_graph
+    res["group_gflop"] = {"p50": percentile(gflops, 0.5) / 1e9, "p99": percentile(gflops, 0.99) / 1e9}
     graph.close()
     for p in plans:
         p.close()
+    del Cs, A, B
     return res
 
 
@@ -653,10 +772,12 @@ def run_shapes(args, sg, torch, ctx, stream):
 
 def run_offgrid(args, sg, torch, ctx, stream):
     """Config 3: 4,096 GEMMs with M, N, K ~ U{1..8192} (seed 3), BF16 out.  The dispatch table is
-    measured on a step-512 grid {512..8192}^3 (4,096 cells; a step-128 grid to 8192 would be
-    262,144 cells), then the shapes run (a) naive pad-to-tile: the plain 256 x 256 kernel
-    predicated over the ragged edges, (b) best-of-N, (c) DP pad/split dispatch."""
-    step, n = 512, 16
+    measured on the grid {step..8192}^3 (step 256 by default: 32,768 cells, the landscape's
+    count; step 128 would be 262,144), then the shapes run (a) naive pad-to-tile: the plain
+    256 x 256 kernel predicated over the ragged edges, (b) best-of-N, (c) DP pad/split
+    dispatch."""
+    step = args.offgrid_step
+    n = 8192 // step
     pool = 8192 * 8192
     A = torch.empty(pool, dtype=torch.bfloat16, device="cuda")
     B = torch.empty(pool, dtype=torch.bfloat16, device="cuda")
@@ -664,10 +785,11 @@ def run_offgrid(args, sg, torch, ctx, stream):
     sg.fill_bf16(A, 3, 0)
     sg.fill_bf16(B, 3, 1)
     torch.cuda.synchronize()
-    variants = [int(v) for v in args.variants.split(",")]
+    variants = [int(v) for v in (args.offgrid_variants or args.variants).split(",")]
     t0 = time.perf_counter()
     table = ctx.build_table(step, n, n, n, variants, A, B, C, c_dtype=sg.BF16,
-                            warmup=args.shape_warmup, reps=args.reps, order_seed=13, stream=stream)
+                            warmup=args.shape_warmup, reps=args.offgrid_reps or args.reps, order_seed=13,
+                            stream=stream)
     table_s = time.perf_counter() - t0
     ctx.set_table(table)
     rng = np.random.default_rng(3)
@@ -691,9 +813,11 @@ def run_offgrid(args, sg, torch, ctx, stream):
     return out
 
 
-def run_serve(args, sg, torch, ctx):
-    """Config 5: Poisson requests over four transformer-layer weights, grouped continuous
-    batching versus per-request dispatch, same tile shape, same arrivals."""
+def run_serve(args, sg, torch, ctx, table=None):
+    """Config 5: Poisson requests over four transformer-layer weights (the full duration), grouped
+    continuous batching versus per-request dispatch, same arrivals and tile classes (M <= 64 on
+    the small tile, the rest on the main tile); then each mode at saturation, closed loop with a
+    fixed number of requests outstanding."""
     shapes = [(4096, 4096), (4096, 11008), (11008, 4096), (4096, 14336)]     # (K, N)
     ws = []
     for i, (K, N) in enumerate(shapes):
@@ -702,17 +826,34 @@ def run_serve(args, sg, torch, ctx):
         ws.append(t)
     torch.cuda.synchronize()
     out = {"rate_req_s": args.serve_rate, "duration_s": args.serve_seconds,
-           "warmup_s": args.serve_warmup, "tile": sg.variant_info(4 * args.serve_tile).name[:-3]}
+           "warmup_s": args.serve_warmup, "tile": sg.variant_info(4 * args.serve_tile).name[:-6],
+           "small_m": args.serve_small_m, "small_tile": sg.variant_info(4 * args.serve_small_tile).name[:-6]}
     for name, mode in (("grouped", sg.SERVE_GROUPED), ("per_request", sg.SERVE_PER_REQUEST)):
         srv = sg.Server(ctx, [(K, N, t.data_ptr(), N) for (K, N), t in zip(shapes, ws)],
                         hbm_budget=args.serve_budget_gb << 30, max_inflight=4, max_group=64,
-                        mode=mode, tile=args.serve_tile, max_m=8192, seed=5)
-        log("serving (%s) %.0f req/s for %.0f s" % (name, args.serve_rate, args.serve_seconds))
-        rep = srv.serve_poisson(args.serve_rate, args.serve_seconds, args.serve_warmup, 5, 8192)
-        srv.close()
-        out[name] = rep
-        log("  p50 %.2f ms p99 %.2f ms, %.1f req/s, %.1f TFLOP/s" % (rep["p50_ms"], rep["p99_ms"],
-                                                                   rep["req_per_s"], rep["tflops"]))
+                        mode=mode, tile=args.serve_tile, max_m=8192, seed=5,
+                        small_m=args.serve_small_m, small_tile=args.serve_small_tile)
+        try:
+            log("serving (%s) %.0f req/s for %.0f s" % (name, args.serve_rate, args.serve_seconds))
+            rep = srv.serve_poisson(args.serve_rate, args.serve_seconds, args.serve_warmup, 5, 8192)
+            out[name] = rep
+            log("  p50 %.2f ms p99 %.2f ms, %.1f req/s, %.1f TFLOP/s, %d launches"
+                % (rep["p50_ms"], rep["p99_ms"], rep["req_per_s"], rep["tflops"], rep["launches"]))
+            if args.serve_saturate > 0:
+                sat = srv.serve_closed(args.serve_outstanding, args.serve_saturate, min(2.0, args.serve_saturate / 4),
+                                       7, 8192)
+                out[name + "_saturated"] = sat
+                log("  saturated (%d outstanding): %.1f req/s, %.1f TFLOP/s, p50 %.2f ms p99 %.2f ms, %d launches"
+                    % (args.serve_outstanding, sat["req_per_s"], sat["tflops"], sat["p50_ms"], sat["p99_ms"],
+                       sat["launches"]))
+        finally:
+            srv.close()
+    if args.serve_saturate > 0:
+        g, p = out["grouped_saturated"], out["per_request_saturated"]
+        out["saturation"] = {"outstanding": args.serve_outstanding, "seconds": args.serve_saturate,
+                             "throughput_ratio": g["req_per_s"] / p["req_per_s"] if p["req_per_s"] else None,
+                             "p99_ratio": g["p99_ms"] / p["p99_ms"] if p["p99_ms"] else None}
+    del ws
     return out
 
 
@@ -721,7 +862,15 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2, help="timed passes over the sweep")
     ap.add_argument("--warmup", type=int, default=1, help="untimed passes before timing")
-    ap.add_argument("--reps", type=int, default=5, help="timed runs per shape (one more is discarded)")
+    ap.add_argument("--reps", type=int, default=5,
+                    help="timed runs per shape in the table measurement (one more is discarded), and "
+                         "the least number of timed runs per shape over all timed passes")
+    ap.add_argument("--reps-per-pass", type=int, default=0,
+                    help="timed runs per shape in each timed pass (0: ceil(reps / steps))")
+    ap.add_argument("--budget", type=float, default=560.0,
+                    help="wall-clock seconds the default run aims to finish in: the grouped and "
+                         "serving legs are skipped (and named in the output) when they would not fit")
+    ap.add_argument("--no-grouped", action="store_true", help="skip the grouped leg of the sweep")
     ap.add_argument("--shape-warmup", type=int, default=5, help="warm-up runs before a pass")
     ap.add_argument("--step", type=int, default=128, help="grid step")
     ap.add_argument("--n", type=int, default=32, help="grid points per axis")
@@ -744,19 +893,25 @@ def main():
                          "concurrent: the DP's M/N split plans with their pieces run at the same time; "
                          "vendor: the vendor GEMM library over the landscape, for context")
     ap.add_argument("--groups", type=int, default=512)
+    ap.add_argument("--offgrid-step", type=int, default=256, help="grid step of the off-grid table")
+    ap.add_argument("--offgrid-variants", default=None, help="variant set of the off-grid table")
+    ap.add_argument("--offgrid-reps", type=int, default=0, help="timed runs per cell of the off-grid table")
     ap.add_argument("--serve-rate", type=float, default=2000.0)
-    ap.add_argument("--serve-seconds", type=float, default=None,
-                    help="default 20 s inside the sweep workload, 60 s for --workload serve")
+    ap.add_argument("--serve-seconds", type=float, default=60.0,
+                    help="duration of each serving run (the serving workload's 60 s)")
     ap.add_argument("--serve-warmup", type=float, default=5.0)
     ap.add_argument("--serve-tile", type=int, default=3)
+    ap.add_argument("--serve-small-m", type=int, default=64)
+    ap.add_argument("--serve-small-tile", type=int, default=6)
+    ap.add_argument("--serve-saturate", type=float, default=12.0,
+                    help="seconds of closed-loop saturation per serving mode (0: skip)")
+    ap.add_argument("--serve-outstanding", type=int, default=64)
     ap.add_argument("--serve-budget-gb", type=int, default=64)
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg of the sweep")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="before the sweep, copy MIB MiB three times with a plain copy kernel (a "
                          "known-size reference for hardware byte counters)")
     args = ap.parse_args()
-    if args.serve_seconds is None:
-        args.serve_seconds = 60.0 if args.workload == "serve" else 20.0
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -764,6 +919,14 @@ def main():
               "run on a single MI355X; runs on %d GPUs are not part of this build" % max(args.gpus, world),
               file=sys.stderr)
         sys.exit(2)
+
+    # the CPU baseline runs first, in worker processes forked before anything touches the GPU
+    cpu = None
+    if args.workload == "sweep" and not args.no_cpu_baseline:
+        log("cpu baseline")
+        cpu = cpu_baseline(args.cpu_seconds, args.seed)
+        log("cpu baseline done (%.0f s since start): %.4f TFLOP/s on %d cores"
+            % (elapsed(), cpu["value"], cpu["cores"]))
 
     import torch
     import paper_2605_29752_amd as sg
@@ -903,8 +1066,6 @@ def main():
         del src, dst
 
     variants = [int(v) for v in args.variants.split(",")]
-    if args.plain_variant not in variants:
-        variants = [args.plain_variant] + variants
     t_tab = time.perf_counter()
     if args.table:
         table = sg.Table.load(args.table)
@@ -917,21 +1078,38 @@ def main():
         if args.save_table:
             table.save(args.save_table)
     table_s = time.perf_counter() - t_tab
-    log("table ready in %.1f s" % table_s)
+    log("table ready in %.1f s (%.0f s since start)" % (table_s, elapsed()))
     ctx.set_table(table)
 
     T0all = table.values(3)
     T0best, T1, T2 = table.values(0), table.values(1), table.values(2)
-    plain_row = variants.index(args.plain_variant)
+    # the plain stack: one tile shape with no split for every shape -- the measured variant
+    # fastest at the grid's largest cell (the single-kernel choice a user tuning on the big cube
+    # would make); the paper's default 256 x 256 tile is reported beside it
+    no_split = [r for r, v in enumerate(variants) if sg.variant_info(v).splits == 1]
+    plain_row = min(no_split, key=lambda r: T0all[r][-1, -1, -1])
+    plain_variant = variants[plain_row]
+    default_row = variants.index(0) if 0 in variants else None
 
     rng = np.random.default_rng(args.order_seed)
     cells = rng.permutation(n ** 3)
     idx = np.array(np.unravel_index(cells, (n, n, n))).T
     shapes = [(int((i + 1) * step), int((j + 1) * step), int((k + 1) * step)) for i, j, k in idx]
+    # timed launches per shape per pass: enough that the timed passes together give every shape
+    # at least `reps` timed runs (each run after one untimed run of the same shape, as in the
+    # table's protocol)
+    reps_pass = args.reps_per_pass or max(1, -(-args.reps // max(args.steps, 1)))
 
-    def one_pass():
-        return ctx.sweep(shapes, A, B, C, mode=sg.MODE_DP, c_dtype=sg.BF16,
-                         warmup=args.shape_warmup, reps=args.reps, stream=stream)
+    def one_pass(mode=sg.MODE_DP, variant=0, reps=reps_pass, interval=False):
+        ctx.set_interval_timing(interval)
+        sec = ctx.sweep(shapes, A, B, C, mode=mode, variant=variant, c_dtype=sg.BF16,
+                        warmup=args.shape_warmup, reps=reps, stream=stream)
+        return sec, (ctx.interval_times(len(shapes)) if interval else None)
+
+    def to_grid(v):
+        out = np.zeros(n ** 3)
+        out[cells] = v
+        return out.reshape(n, n, n)
 
     for w in range(args.warmup):
         log("warm-up pass %d" % w)
@@ -942,41 +1120,74 @@ def main():
     ksec = np.zeros(sg.num_variants())
     kflops = np.zeros(sg.num_variants())
     t0 = time.perf_counter()
-    for s in range(args.steps):
-        sec = one_pass()
+    for s_ in range(args.steps):
+        sec, _ = one_pass()
         la, se, fl = ctx.kernel_times()
         launches += la
         ksec += se
         kflops += fl
-        passes.append(sec)
-        log("timed pass %d done" % s)
+        passes.append(to_grid(sec))
+        log("timed pass %d done (%.0f s since start)" % (s_, elapsed()))
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms_per_step = wall / args.steps * 1e3
+    exec_sec = np.mean(passes, axis=0)
+    # gap-included executions: every run of the DP plans and of the plain variant timed as a
+    # whole between two stream markers (one pass each, three marker-timed runs per shape)
+    log("interval-timed passes (DP plans, plain %s)" % sg.variant_info(plain_variant).name)
+    _, iv = one_pass(reps=3, interval=True)
+    exec_iv = to_grid(iv)
+    _, p_iv = one_pass(sg.MODE_VARIANT, plain_variant, 3, interval=True)
+    plain_exec_iv = to_grid(p_iv)
 
-    exec_sec = np.zeros(n ** 3)
-    exec_sec[cells] = np.mean(passes, axis=0)
-    exec_sec = exec_sec.reshape(n, n, n)
-
+    M3 = sizes[:, None, None]
+    N3 = sizes[None, :, None]
+    K3 = sizes[None, None, :]
+    W3 = 2.0 * M3 * N3 * K3
+    pname = "plain_%s" % sg.variant_info(plain_variant).name
     stack_secs = {
-        "plain_%s" % sg.variant_info(args.plain_variant).name: T0all[plain_row],
+        pname: T0all[plain_row],
         "best_of_%d" % len(variants): T0best,
         "dp_pad_table": T1,
         "dp_split_pad_table": T2,
         "dp_split_pad_executed": exec_sec,
     }
+    if default_row is not None and default_row != plain_row:
+        stack_secs["paper_default_256x256x64_s1"] = T0all[default_row]
     stacks = {name: stack_stats(sg, sec, sizes) for name, sec in stack_secs.items()}
     # best single variant by mean over the sweep
     means = [stack_stats(sg, T0all[r], sizes)["mean_tflops"] for r in range(len(variants))]
     best_single = variants[int(np.argmax(means))]
     stacks["best_single_%s" % sg.variant_info(best_single).name] = \
         stack_stats(sg, T0all[variants.index(best_single)], sizes)
+    # gap-included (marker-interval) executions of the DP and plain stacks
+    stacks["dp_split_pad_executed_interval"] = stack_stats(sg, exec_iv, sizes)
+    stacks[pname + "_executed_interval"] = stack_stats(sg, plain_exec_iv, sizes)
+    for st in stacks.values():
+        st["relative_roughness_3d"] = st["roughness_3d"] / st["mean_tflops"]
+
+    # noise floor: the roughness that measurement noise alone puts into one pass (from the
+    # difference of consecutive passes, scaled by 1/sqrt 2), and what is left of it in the
+    # mean of all passes (1/sqrt(passes) of that)
+    noise = {}
+    if len(passes) >= 2:
+        tfp = [W3 / p / 1e12 for p in passes]
+        single = [sg.landscape_stats((tfp[i] - tfp[i + 1]) / np.sqrt(2.0)) for i in range(len(tfp) - 1)]
+        r1 = float(np.mean([x["roughness_3d"] for x in single]))
+        sl1 = float(np.mean([np.mean([sg.roughness(row) for row in ((tfp[i] - tfp[i + 1]) / np.sqrt(2.0))[:, :, -1]])
+                             for i in range(len(tfp) - 1)]))
+        cv = float(np.median(np.std(np.array(passes), axis=0) / exec_sec))
+        noise = {"single_pass_roughness_3d": r1, "single_pass_roughness_slice": sl1,
+                 "mean_of_passes_roughness_3d": r1 / np.sqrt(len(passes)),
+                 "mean_of_passes_roughness_slice": sl1 / np.sqrt(len(passes)),
+                 "median_cv_across_passes": cv, "passes": len(passes), "timed_runs_per_shape_per_pass": reps_pass}
 
     # dominant kernel: the tile kernel with the most execution time, over every variant that
     # launches it (the split-K variants of a tile run the same kernel; their accounted time is
     # the tile kernel's own, the reduction excluded)
-    tile_keys = sorted({(sg.variant_info(v).bm, sg.variant_info(v).bn) for v in range(sg.num_variants())})
-    tile_of = np.array([tile_keys.index((sg.variant_info(v).bm, sg.variant_info(v).bn))
+    tile_keys = sorted({(sg.variant_info(v).bm, sg.variant_info(v).bn, sg.variant_info(v).bk)
+                        for v in range(sg.num_variants())})
+    tile_of = np.array([tile_keys.index((sg.variant_info(v).bm, sg.variant_info(v).bn, sg.variant_info(v).bk))
                         for v in range(sg.num_variants())])
     ntiles = len(tile_keys)
     t_sec = np.array([ksec[tile_of == t].sum() for t in range(ntiles)])
@@ -984,12 +1195,12 @@ def main():
     t_flops = np.array([kflops[tile_of == t].sum() for t in range(ntiles)])
     dom_tile = int(np.argmax(t_sec))
     vi = sg.variant_info(int(np.flatnonzero(tile_of == dom_tile)[0]))
-    # every grid shape is aligned, so its tiles run the direct-to-LDS kernel
-    dom_kernel = "sg_gemm_tile_dma<%d, %d>" % (vi.bm, vi.bn)
+    dom_kernel = kernel_name(sg, vi.id)
     achieved = t_flops[dom_tile] / t_sec[dom_tile] / 1e12
     dom_variants = [sg.variant_info(v).name for v in np.flatnonzero((tile_of == dom_tile) & (launches > 0))]
     ex = stacks["dp_split_pad_executed"]
-    plain = stacks["plain_%s" % sg.variant_info(args.plain_variant).name]
+    plain = stacks[pname]
+    bestn = stacks["best_of_%d" % len(variants)]
 
     actions = {}
     for c in range(n ** 3):
@@ -997,6 +1208,13 @@ def main():
         a = table.lookup(int((i + 1) * step), int((j + 1) * step), int((k + 1) * step))["action"]
         actions[a] = actions.get(a, 0) + 1
     names = {0: "as_is", 1: "pad", 2: "split_m", 3: "split_n", 4: "split_k"}
+
+    def gain(a, b):
+        return {"mean": a["mean_tflops"] / b["mean_tflops"] - 1.0,
+                "roughness_3d": a["roughness_3d"] / b["roughness_3d"] - 1.0,
+                "texture_3d": a["texture_3d"] / b["texture_3d"] - 1.0,
+                "roughness_slice": a["slice_k%d_roughness_n" % maxdim] / b["slice_k%d_roughness_n" % maxdim] - 1.0,
+                "relative_roughness_3d": a["relative_roughness_3d"] / b["relative_roughness_3d"] - 1.0}
 
     result = {
         "metric": "mean BF16 TFLOPs + roughness over 32,768-shape sweep; served p50/p99 latency",
@@ -1016,15 +1234,18 @@ def main():
                                "output, executed through best-of-N + DP pad/split dispatch table"
                                % (step, maxdim, step, n ** 3),
                    "shapes": n ** 3, "variants": [sg.variant_info(v).name for v in variants],
-                   "reps_per_shape": args.reps, "order": "randomized (seed %d)" % args.order_seed},
+                   "table_reps_per_shape": args.reps, "timed_runs_per_shape_per_pass": reps_pass,
+                   "order": "randomized (seed %d)" % args.order_seed},
         "roughness_3d": ex["roughness_3d"],
         "roughness_slice_k%d" % maxdim: ex["slice_k%d_roughness_n" % maxdim],
+        "relative_roughness_3d": ex["relative_roughness_3d"],
         "peak_tflops": ex["peak_tflops"],
         "frac_of_bf16_peak_mean": ex["mean_tflops"] / PEAK_BF16_TFLOPS,
-        "gain_vs_plain": {"mean": ex["mean_tflops"] / plain["mean_tflops"] - 1.0,
-                          "roughness_3d": ex["roughness_3d"] / plain["roughness_3d"] - 1.0,
-                          "roughness_slice": ex["slice_k%d_roughness_n" % maxdim] /
-                          plain["slice_k%d_roughness_n" % maxdim] - 1.0},
+        "executed_interval_mean_tflops": stacks["dp_split_pad_executed_interval"]["mean_tflops"],
+        "plain_variant": sg.variant_info(plain_variant).name,
+        "gain_vs_plain": gain(ex, plain),
+        "gain_vs_best_of_n": gain(ex, bestn),
+        "noise_floor": noise,
         "stacks": stacks,
         "first_principles": first_principles(sg, stack_secs, sizes, args.step, n),
         "dp_actions": {names[a]: c / n ** 3 for a, c in sorted(actions.items())},
@@ -1043,17 +1264,40 @@ def main():
                      "flop_per_launch": t_flops[dom_tile] / max(t_launch[dom_tile], 1)},
         "device": props.name,
     }
+    if cpu is not None:
+        result["cpu_baseline"] = cpu
+    skipped = []
+    # grouped batching (config 4) with the table set: per-call best-of-N / DP baselines
+    if not args.no_grouped:
+        if elapsed() + 60 < args.budget:
+            g = run_grouped(args, sg, torch, ctx, torch.cuda.Stream(), reps=min(args.steps, 5))
+            result["grouped"] = g
+            log("grouped done (%.0f s since start)" % elapsed())
+        else:
+            skipped.append("grouped")
+    ctx.set_table(None)
     if not args.no_serve:
-        srv = run_serve(args, sg, torch, ctx)
-        result["served_p50_ms"] = srv["grouped"]["p50_ms"]
-        result["served_p99_ms"] = srv["grouped"]["p99_ms"]
-        result["serving"] = srv
-    if not args.no_cpu_baseline:
-        log("cpu baseline")
-        result["cpu_baseline"] = cpu_baseline(args.cpu_seconds, args.seed)
+        need = 2 * (args.serve_seconds + args.serve_saturate + 15)
+        if elapsed() + need < args.budget:
+            srv = run_serve(args, sg, torch, ctx, table)
+            result["served_p50_ms"] = srv["grouped"]["p50_ms"]
+            result["served_p99_ms"] = srv["grouped"]["p99_ms"]
+            result["serving"] = srv
+            log("serving done (%.0f s since start)" % elapsed())
+        else:
+            skipped.append("serving")
+    if skipped:
+        result["skipped_for_time_budget"] = skipped
+    result["wall_s"] = elapsed()
     if args.dump:
         np.savez_compressed(args.dump, sizes=sizes, T0=T0all, T0best=T0best, T1=T1, T2=T2,
-                            executed=exec_sec, variants=np.array(variants))
+                            executed=exec_sec, executed_interval=exec_iv, passes=np.array(passes),
+                            variants=np.array(variants), plain_interval=plain_exec_iv)
+    # release everything before the interpreter shuts down (HIP status checked on each)
+    table.close()
+    ctx.close()
+    del A, B, C
+    torch.cuda.synchronize()
     print(json.dumps(result), flush=True)
 
 

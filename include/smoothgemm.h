@@ -85,8 +85,9 @@ int sg_ctx_reserve_workspace(sg_ctx* ctx, size_t bytes);
 
 /* ---- GEMM ----------------------------------------------------------------------------------
  * Paper-form call (Sec. 7.1 problem statement): C (FP32, ldc = N) = A (lda = K) * B (ldb = N).
- * Device pointers; uses a per-device default context and the null stream, SG_MODE_DEFAULT.
- * M == 0 or N == 0: no-op.  K == 0: C is set to zero. */
+ * Device pointers; runs on the current device's default context (sg_default_ctx) and the null
+ * stream in SG_MODE_DEFAULT: the DP plan when a table was lent with sg_set_default_table, else
+ * the plain variant.  M == 0 or N == 0: no-op.  K == 0: C is set to zero. */
 int gemm_bf16_nn(int64_t M, int64_t N, int64_t K, const void* A, const void* B, void* C);
 
 typedef struct sg_gemm_args {
@@ -122,10 +123,16 @@ int gemm_bf16_nn_ex_noalloc(sg_ctx* ctx, const sg_gemm_args* args, void* stream)
 size_t sg_noalloc_scratch_bytes(void);
 
 /* ---- kernel variants (the tile family) ----------------------------------------------------
- * Variant v = 4 t + log2(S): tile t (BM x BN, 256 threads, MFMA 16x16x32 BF16) and a parallel
- * split-K factor S in {1, 2, 4, 8} (S > 1: FP32 partials in the workspace, then a fixed-order
- * reduction).  Tiles 0..7: 256x256, 256x128, 128x256, 128x128, 128x64, 64x128, 64x64, and 64x64
- * with 128-deep K stages (for shapes with few tiles; per-call only, not in grouped launches).
+ * Variant v = 4 t + log2(S), v < 32: tile t (BM x BN, 256 threads, MFMA 16x16x32 BF16) and a
+ * parallel split-K factor S in {1, 2, 4, 8} (S > 1: FP32 partials in the workspace, then a
+ * fixed-order reduction).  Tiles 0..7: 256x256, 256x128, 128x256, 128x128, 128x64, 64x128,
+ * 64x64, and 64x64 with 128-deep K stages (for shapes with few tiles; per-call only, not in
+ * grouped launches).
+ * Variant 32 + t, t = 0..6: stream-K on tile t -- exactly as many work-groups as the GPU keeps
+ * resident, each taking an equal share of the (tile, K stage) iterations of all tiles; a tile
+ * split between work-groups is summed from FP32 partials (workspace) by a fix-up kernel in K
+ * order, so results are bit-reproducible.  splits = 0 marks these variants.  Needs a workspace
+ * (like S > 1); there is no memory-only twin.
  * bk is the K granularity of a split (64; 128 for tile 7), lds_bytes the LDS of the aligned
  * kernel (its ring of K stages). */
 typedef struct sg_variant_info {
@@ -156,7 +163,8 @@ int sg_landscape_stats(const double* tflops, int nM, int nN, int nK, sg_stats* o
  * sg_optimal_landscape (Sec. 9.2): 2MNK / t_opt, t_opt = min over the ntiles square tile edges T
  *   of max(2MNK / (peak * eta(T)), t_mem), eta(T) = W_T / (ceil(W_T / C) C) the fraction of the
  *   launched core-slots that work (wave quantization), t_mem = (2MK + 2KN + c_bytes MN) / BW
- *   (per-channel utilisation taken as 1: the HBM address hash is not public).
+ *   (per-channel utilisation taken as 1: the HBM address hash is not public; the paper's GDDR6
+ *   channel term is sg_optimal_landscape_ch).
  * sg_kol_grade (Sec. 10.2-10.3): attainment tau = mean(actual) / mean(optimal); roughness ratio
  *   rho = R(actual) / R(optimal), R the N-axis roughness averaged over every line along N;
  *   bands of Table 19 (tau: < 0.5, < 0.75, < 0.95, else; rho: > 3, > 2, > 1.25, else) and level
@@ -168,6 +176,14 @@ struct sg_grid;
 int sg_ideal_landscape(const struct sg_grid* grid, const sg_hw* hw, int tile, double* out);
 int sg_optimal_landscape(const struct sg_grid* grid, const sg_hw* hw, const int* tiles, int ntiles,
                          int c_bytes, double* out);
+/* The same with the paper's memory-channel term (Sec. 9.2): t_mem = 2MK / (BW eta_A) +
+ * 2KN / (BW eta_B) + c_bytes MN / (BW eta_D), where a tensor with leading dimension L (K for A,
+ * N for B and D) moved in rows of 256 elements of e bytes over `channels` channels striped in
+ * `interleave`-byte blocks keeps eta = min(channels, w channels / gcd(s, channels)) / channels
+ * of them busy, w = min(channels, 256 e / interleave), s = (L e / interleave) mod channels.
+ * channels = 0 takes every eta as 1 (sg_optimal_landscape). */
+int sg_optimal_landscape_ch(const struct sg_grid* grid, const sg_hw* hw, const int* tiles, int ntiles,
+                            int c_bytes, int channels, int interleave, double* out);
 int sg_kol_grade(const double* actual, const double* optimal, int n_m, int n_n, int n_k, sg_kol* out);
 
 /* ---- four-surface decomposition (paper Sec. 4) ------------------------------------------------
@@ -209,6 +225,15 @@ int sg_sweep(sg_ctx* ctx, const sg_shape* shapes, int64_t n, int mode, int varia
  * flops[v] algorithmic FLOP (2 M N K of the data shape of each launch). Arrays hold
  * sg_num_variants() entries. */
 int sg_sweep_kernel_times(const sg_ctx* ctx, int64_t* launches, double* seconds, double* flops);
+/* Interval timing (on = 1; default 0): after a shape's timed runs, sg_sweep runs it `reps`
+ * more times, each run between two markers recorded on the stream and with no timing events
+ * of its own inside, so that each run is timed as a whole -- the kernels, the device-side gaps
+ * between them and any host launch gap (for a multi-kernel plan, the time a caller actually
+ * waits).  sg_sweep's own out_sec keeps the kernel-time sum; the interval means of the most
+ * recent sweep (n = its shape count) are read with sg_sweep_interval_times (SG_EINVAL if that
+ * sweep ran without interval timing or had another shape count). */
+int sg_ctx_set_interval_timing(sg_ctx* ctx, int on);
+int sg_sweep_interval_times(const sg_ctx* ctx, double* out_sec, int64_t n);
 
 /* ---- memory-subsystem study (paper Sec. 5) -----------------------------------------------------
  * Bandwidth microbenchmarks over the GEMM's buffers: read A (M x K), read B (K x N), read C and
@@ -285,10 +310,18 @@ int sg_table_plan_leaves(const sg_table* t, int64_t M, int64_t N, int64_t K, int
 /* Binary file with a fingerprint (GPU architecture, compute-unit count, HIP runtime version, grid,
  * variant set, output type); load refuses a mismatch with SG_EMISMATCH unless `force` != 0.
  * Loading requires the current HIP device only when force == 0. */
+/* Number of grouped-launch schedules recorded in the table (see sg_group_plan_create). */
+int sg_table_group_count(const sg_table* t, int64_t* n);
 int sg_table_save(const sg_table* t, const char* path);
 int sg_table_load(const char* path, int force, sg_table** out);
 /* Borrow the table for SG_MODE_DEFAULT / BEST / DP calls (NULL clears). */
 int sg_ctx_set_table(sg_ctx* ctx, const sg_table* t);
+/* The per-device default context that gemm_bf16_nn uses (created on first use; the library owns
+ * it, and a caller that destroys it gets a fresh one on next use).  sg_set_default_table lends
+ * it a table, so that the paper-form call runs the DP plan of Sec. 7.1 by O(1) lookup (NULL
+ * clears: the plain variant again).  The table must outlive its use. */
+int sg_default_ctx(int device, sg_ctx** out);
+int sg_set_default_table(int device, const sg_table* t);
 
 /* ---- grouped batching: many independent GEMMs in one persistent launch -------------------
  * One problem per entry: device pointers, row-major, the same conventions as sg_gemm_args
@@ -311,18 +344,25 @@ typedef struct sg_group_cfg {
     int order;      /* 0: longest K first (greedy longest-processing-time), 1: as given */
 } sg_group_cfg;
 typedef struct sg_group_plan sg_group_plan;
-/* cfg == NULL autotunes: every tile shape is timed on this group (one warm-up, best of three)
- * and the fastest kept.  Synchronises `stream`. */
+/* cfg == NULL autotunes the schedule (tile shape, resident grid, queue order): every tile shape
+ * is timed on this group at full residency with the longest-K-first queue (one warm-up, best of
+ * three), then the two fastest tiles also with the queue in the given order and with smaller
+ * grids (one work-group per CU, half the resident count), and the fastest configuration kept.
+ * When ctx holds a dispatch table, the winner is recorded in the table under a key of the
+ * problem list (shapes, alignment classes, c_dtype), and a later cfg == NULL plan of the same
+ * problem list takes it from there without timing anything (O(1) lookup); saved tables carry
+ * these schedules.  Synchronises `stream`. */
 int sg_group_plan_create(sg_ctx* ctx, int G, const sg_problem* probs, int c_dtype,
                          const sg_group_cfg* cfg, void* stream, sg_group_plan** out);
 int sg_group_plan_launch(sg_group_plan* plan, void* stream);
-/* Replace the problems (same count).  Returns SG_EAGAIN when the tile count changed: graphs
- * that captured this plan must then be captured again. */
+/* Replace the problems (same count).  Returns SG_EAGAIN when the tile count, the grid or the
+ * kernel (all problems aligned or not) changed: graphs that captured this plan must then be
+ * captured again (they would replay the old launch). */
 int sg_group_plan_update(sg_group_plan* plan, const sg_problem* probs, void* stream);
 int sg_group_plan_info(const sg_group_plan* plan, sg_group_cfg* cfg, int* total_tiles, int* grid,
                        double* flops);
 int sg_group_plan_destroy(sg_group_plan* plan);
-/* One-shot form: plan (cfg NULL = tile 128x128), launch, wait, free. */
+/* One-shot form: plan (cfg NULL = autotune, as sg_group_plan_create), launch, wait, free. */
 int sg_gemm_grouped(sg_ctx* ctx, int G, const sg_problem* probs, int c_dtype,
                     const sg_group_cfg* cfg, void* stream);
 
@@ -344,9 +384,13 @@ int sg_graph_destroy(sg_graph* graph);
  * submitted at any time from any thread.  A worker thread admits pending requests, oldest
  * first, while their A (M x K) and C (M x N) fit in an HBM budget carved from one device
  * allocation; stages each admitted request's A (copied from a resident pool of N(0, a_scale)
- * activations at a per-request offset derived from (seed, id)); and launches the admitted
- * requests as one grouped kernel on any free stream slot, so new work overlaps running work.
- * SG_SERVE_PER_REQUEST launches every request on its own (the per-call baseline).  Times are
+ * activations at a per-request offset derived from (seed, id)); and launches admitted requests
+ * as one grouped kernel on any free stream slot, so new work overlaps running work.  Every
+ * request belongs to a tile class (small_tile for M <= small_m, else tile); a launch takes the
+ * oldest admitted request and up to max_group - 1 admitted requests after it of its class.  A
+ * launch of one request runs the tile kernel directly (no descriptors, no work queue).
+ * SG_SERVE_PER_REQUEST launches every request on its own (the per-call baseline), with the same
+ * tile classes.  Times are
  * seconds on the server's clock (sg_server_now).  The caller owns the weights and keeps them
  * alive for the server's lifetime; the server owns request memory. */
 #define SG_SERVE_GROUPED      0
@@ -358,13 +402,15 @@ typedef struct sg_server_cfg {
     int max_group;              /* requests per grouped launch, 1..4096                          */
     int queue_cap;              /* pending requests before submit returns SG_EAGAIN              */
     int mode;                   /* SG_SERVE_GROUPED or SG_SERVE_PER_REQUEST                      */
-    int tile;                   /* tile shape index 0..6 (per-request mode: the same tile, S = 1) */
+    int tile;                   /* tile shape index 0..6 of requests with M > small_m (S = 1)      */
     int keep_results;           /* 1: C stays allocated until sg_server_release                  */
     int n_weights;
     const sg_weight* weights;   /* copied at creation                                            */
     int64_t max_m;              /* largest request M                                             */
     uint64_t seed;              /* activation pool and per-request offsets                       */
     double a_scale;             /* activation standard deviation                                 */
+    int64_t small_m;            /* requests with M <= small_m run with small_tile (0: none)      */
+    int small_tile;             /* tile shape index 0..6 for those skinny requests               */
 } sg_server_cfg;
 typedef struct sg_request { uint64_t id; int64_t M; int weight; } sg_request;
 typedef struct sg_completion {
@@ -373,6 +419,7 @@ typedef struct sg_completion {
     int weight;
     int status;                 /* SG_OK or the failure code                                     */
     int64_t a_offset;           /* element offset of A in the activation pool                    */
+    int tile;                   /* tile shape the request ran with                               */
     double t_arrival, t_admit, t_launch, t_done;
     const void* A;              /* device; valid until release when keep_results, else NULL      */
     const void* C;
@@ -404,6 +451,12 @@ typedef struct sg_serve_report {
 } sg_serve_report;
 int sg_serve_poisson(sg_server* server, double rate, double duration_s, double warmup_s,
                      uint64_t seed, int64_t max_m, sg_serve_report* rep);
+/* Closed-loop load (saturation): keeps `outstanding` requests in the server -- a new one is
+ * submitted as each completes -- for duration_s, requests drawn as in sg_serve_poisson; reports
+ * the requests that arrived in [warmup_s, duration_s): throughput and nearest-rank p50 / p99 of
+ * (done - submit).  `launches` counts this run's launches only. */
+int sg_serve_closed(sg_server* server, int outstanding, double duration_s, double warmup_s,
+                    uint64_t seed, int64_t max_m, sg_serve_report* rep);
 
 /* ---- device operand generator (the seeded counter generator, on the GPU) ---------------------
  * Element idx of stream `stream` under `seed`: SplitMix64 word

@@ -8,6 +8,7 @@ from __future__ import annotations
 
 import ctypes
 import os
+import sys
 from dataclasses import dataclass
 from typing import Optional, Sequence
 
@@ -85,6 +86,8 @@ _SIGS = {
     "sg_ctx_set_progress": (_i32, [_p, _i32]),
     "sg_ctx_reserve_workspace": (_i32, [_p, ctypes.c_size_t]),
     "sg_ctx_set_table": (_i32, [_p, _p]),
+    "sg_default_ctx": (_i32, [_i32, ctypes.POINTER(_p)]),
+    "sg_set_default_table": (_i32, [_i32, _p]),
     "gemm_bf16_nn": (_i32, [_i64, _i64, _i64, _p, _p, _p]),
     "gemm_bf16_nn_ex": (_i32, [_p, ctypes.POINTER(sg_gemm_args), _p]),
     "gemm_bf16_nn_ex_noalloc": (_i32, [_p, ctypes.POINTER(sg_gemm_args), _p]),
@@ -95,10 +98,14 @@ _SIGS = {
     "sg_landscape_stats": (_i32, [_p, _i32, _i32, _i32, ctypes.POINTER(sg_stats)]),
     "sg_ideal_landscape": (_i32, [ctypes.POINTER(sg_grid), ctypes.POINTER(sg_hw), _i32, _p]),
     "sg_optimal_landscape": (_i32, [ctypes.POINTER(sg_grid), ctypes.POINTER(sg_hw), _p, _i32, _i32, _p]),
+    "sg_optimal_landscape_ch": (_i32, [ctypes.POINTER(sg_grid), ctypes.POINTER(sg_hw), _p, _i32, _i32, _i32,
+                                       _i32, _p]),
     "sg_kol_grade": (_i32, [_p, _p, _i32, _i32, _i32, ctypes.POINTER(sg_kol)]),
     "sg_decompose": (_i32, [_p, _i64, _p, _p, ctypes.POINTER(sg_hw), _i32, _p, _p, ctypes.POINTER(sg_decomp)]),
     "sg_sweep": (_i32, [_p, _p, _i64, _i32, _i32, _i32, _i32, _i32, _p, _p, _p, _p, _p]),
     "sg_sweep_kernel_times": (_i32, [_p, _p, _p, _p]),
+    "sg_ctx_set_interval_timing": (_i32, [_p, _i32]),
+    "sg_sweep_interval_times": (_i32, [_p, _p, _i64]),
     "sg_table_from_t0": (_i32, [ctypes.POINTER(sg_grid), _p, _p, _i32, ctypes.POINTER(_p)]),
     "sg_table_build": (_i32, [_p, ctypes.POINTER(sg_grid), _p, _i32, _i32, _i32, _i32,
                               ctypes.c_uint64, _p, _p, _p, _p, ctypes.POINTER(_p)]),
@@ -108,6 +115,7 @@ _SIGS = {
     "sg_table_values": (_i32, [_p, _i32, _p, _i64]),
     "sg_table_variants": (_i32, [_p, _p, _i32, ctypes.POINTER(_i32)]),
     "sg_table_plan_leaves": (_i32, [_p, _i64, _i64, _i64, ctypes.POINTER(_i32)]),
+    "sg_table_group_count": (_i32, [_p, ctypes.POINTER(_i64)]),
     "sg_table_save": (_i32, [_p, ctypes.c_char_p]),
     "sg_table_load": (_i32, [ctypes.c_char_p, _i32, ctypes.POINTER(_p)]),
     "sg_fill_bf16": (_i32, [_p, _i64, ctypes.c_uint64, ctypes.c_uint64, _i64, _i32, _d, _p]),
@@ -135,6 +143,7 @@ _SIGS = {
     "sg_server_stats_get": (_i32, [_p, _p]),
     "sg_server_destroy": (_i32, [_p]),
     "sg_serve_poisson": (_i32, [_p, _d, _d, _d, ctypes.c_uint64, _i64, _p]),
+    "sg_serve_closed": (_i32, [_p, _i32, _d, _d, ctypes.c_uint64, _i64, _p]),
 }
 
 SERVE_GROUPED, SERVE_PER_REQUEST = 0, 1
@@ -148,7 +157,7 @@ class sg_server_cfg(ctypes.Structure):
     _fields_ = [("hbm_budget", ctypes.c_size_t), ("max_inflight", _i32), ("max_group", _i32),
                 ("queue_cap", _i32), ("mode", _i32), ("tile", _i32), ("keep_results", _i32),
                 ("n_weights", _i32), ("weights", ctypes.POINTER(sg_weight)), ("max_m", _i64),
-                ("seed", ctypes.c_uint64), ("a_scale", _d)]
+                ("seed", ctypes.c_uint64), ("a_scale", _d), ("small_m", _i64), ("small_tile", _i32)]
 
 
 class sg_request(ctypes.Structure):
@@ -157,7 +166,7 @@ class sg_request(ctypes.Structure):
 
 class sg_completion(ctypes.Structure):
     _fields_ = [("ticket", ctypes.c_uint64), ("id", ctypes.c_uint64), ("M", _i64), ("N", _i64),
-                ("K", _i64), ("weight", _i32), ("status", _i32), ("a_offset", _i64),
+                ("K", _i64), ("weight", _i32), ("status", _i32), ("a_offset", _i64), ("tile", _i32),
                 ("t_arrival", _d), ("t_admit", _d), ("t_launch", _d), ("t_done", _d),
                 ("A", _p), ("C", _p)]
 
@@ -204,6 +213,13 @@ def lib():
             f.argtypes = args
         _lib = L
     return _lib
+
+
+def _live() -> bool:
+    """Whether library calls from a finaliser are still safe: at interpreter shutdown the HIP
+    runtime may already be tearing down, so objects still alive then are left to the process
+    exit instead of being destroyed (close() them explicitly to release them earlier)."""
+    return _lib is not None and not sys.is_finalizing()
 
 
 def declared_symbols() -> Sequence[str]:
@@ -281,12 +297,14 @@ def ideal_landscape(step: int, n_m: int, n_n: int, n_k: int, tile: int = 256, hw
 
 
 def optimal_landscape(step: int, n_m: int, n_n: int, n_k: int, tiles=(256, 128, 64), c_bytes: int = 2,
-                      hw=MI355X) -> np.ndarray:
-    """First-principles optimal landscape over the grid (paper Sec. 9.2), TFLOP/s."""
+                      hw=MI355X, channels: int = 0, interleave: int = 256) -> np.ndarray:
+    """First-principles optimal landscape over the grid (paper Sec. 9.2), TFLOP/s; channels > 0
+    adds the memory-channel utilisation term (0: every channel share taken as 1)."""
     out = np.zeros((n_m, n_n, n_k), dtype=np.float64)
     g = sg_grid(step, n_m, n_n, n_k)
     t = (ctypes.c_int * len(tiles))(*tiles)
-    check(lib().sg_optimal_landscape(ctypes.byref(g), ctypes.byref(_hw(hw)), t, len(tiles), c_bytes, _arr(out)))
+    check(lib().sg_optimal_landscape_ch(ctypes.byref(g), ctypes.byref(_hw(hw)), t, len(tiles), c_bytes,
+                                        channels, interleave, _arr(out)))
     return out
 
 
@@ -328,10 +346,14 @@ class Table:
     def __init__(self, handle: int):
         self.handle = ctypes.c_void_p(handle)
 
-    def __del__(self):
+    def close(self):
         if getattr(self, "handle", None) and self.handle.value and _lib is not None:
-            _lib.sg_table_free(self.handle)
-            self.handle = ctypes.c_void_p(0)
+            h, self.handle = self.handle, ctypes.c_void_p(0)
+            check(_lib.sg_table_free(h))
+
+    def __del__(self):
+        if _live():
+            self.close()
 
     @staticmethod
     def from_t0(step: int, n_m: int, n_n: int, n_k: int, T0: np.ndarray, variants) -> "Table":
@@ -381,6 +403,12 @@ class Table:
         check(lib().sg_table_variants(self.handle, _arr(ids), ids.size, ctypes.byref(n)))
         return [int(x) for x in ids[:n.value]]
 
+    def group_schedules(self) -> int:
+        """Grouped-launch schedules the grouped autotuner has recorded in this table."""
+        n = ctypes.c_int64()
+        check(lib().sg_table_group_count(self.handle, ctypes.byref(n)))
+        return n.value
+
     def plan_leaves(self, M: int, N: int, K: int) -> int:
         n = ctypes.c_int()
         check(lib().sg_table_plan_leaves(self.handle, M, N, K, ctypes.byref(n)))
@@ -398,15 +426,14 @@ class Context:
         self._table = None
 
     def close(self):
-        if self.handle and self.handle.value:
-            lib().sg_ctx_destroy(self.handle)
-            self.handle = ctypes.c_void_p(0)
+        """Destroy the context (raises with the HIP status if its release reported an error)."""
+        if getattr(self, "handle", None) and self.handle.value:
+            h, self.handle = self.handle, ctypes.c_void_p(0)
+            check(lib().sg_ctx_destroy(h))
 
     def __del__(self):
-        try:
+        if _live():
             self.close()
-        except Exception:
-            pass
 
     def set_plain_variant(self, v: int):
         check(lib().sg_ctx_set_plain_variant(self.handle, v))
@@ -470,6 +497,16 @@ class Context:
                              _stream_ptr(stream)))
         return out
 
+    def set_interval_timing(self, on: bool):
+        """Also time every sweep run between two stream markers (gaps included)."""
+        check(lib().sg_ctx_set_interval_timing(self.handle, 1 if on else 0))
+
+    def interval_times(self, n: int) -> np.ndarray:
+        """Per-shape marker-to-marker mean seconds of the most recent sweep (n shapes)."""
+        out = np.zeros(n, dtype=np.float64)
+        check(lib().sg_sweep_interval_times(self.handle, _arr(out), n))
+        return out
+
     def kernel_times(self):
         nv = num_variants()
         la = np.zeros(nv, dtype=np.int64)
@@ -526,11 +563,12 @@ class GroupPlan:
 
     def close(self):
         if getattr(self, "handle", None) and self.handle.value and _lib is not None:
-            _lib.sg_group_plan_destroy(self.handle)
-            self.handle = ctypes.c_void_p(0)
+            h, self.handle = self.handle, ctypes.c_void_p(0)
+            check(_lib.sg_group_plan_destroy(h))
 
     def __del__(self):
-        self.close()
+        if _live():
+            self.close()
 
 
 class Graph:
@@ -548,11 +586,12 @@ class Graph:
 
     def close(self):
         if getattr(self, "handle", None) and self.handle.value and _lib is not None:
-            _lib.sg_graph_destroy(self.handle)
-            self.handle = ctypes.c_void_p(0)
+            h, self.handle = self.handle, ctypes.c_void_p(0)
+            check(_lib.sg_graph_destroy(h))
 
     def __del__(self):
-        self.close()
+        if _live():
+            self.close()
 
 
 class Server:
@@ -561,11 +600,13 @@ class Server:
     def __init__(self, ctx: "Context", weights, *, hbm_budget: int, max_inflight: int = 4,
                  max_group: int = 64, queue_cap: int = 1 << 20, mode: int = SERVE_GROUPED,
                  tile: int = 3, keep_results: bool = False, max_m: int = 8192, seed: int = 5,
-                 a_scale: float = 0.02):
-        """weights: [(K, N, B_ptr, ldb), ...] device-resident BF16 matrices."""
+                 a_scale: float = 0.02, small_m: int = 64, small_tile: int = 6):
+        """weights: [(K, N, B_ptr, ldb), ...] device-resident BF16 matrices.  Requests with
+        M <= small_m run with tile shape small_tile, the others with `tile`."""
         self._w = (sg_weight * len(weights))(*[sg_weight(*[int(x) for x in w]) for w in weights])
         cfg = sg_server_cfg(hbm_budget, max_inflight, max_group, queue_cap, mode, tile,
-                            1 if keep_results else 0, len(weights), self._w, max_m, seed, a_scale)
+                            1 if keep_results else 0, len(weights), self._w, max_m, seed, a_scale,
+                            small_m, small_tile)
         h = ctypes.c_void_p()
         check(lib().sg_server_create(ctx.handle, ctypes.byref(cfg), ctypes.byref(h)))
         self.handle = h
@@ -605,13 +646,22 @@ class Server:
                                      ctypes.byref(rep)))
         return {f: getattr(rep, f) for f, _ in sg_serve_report._fields_}
 
+    def serve_closed(self, outstanding: int, duration: float, warmup: float, seed: int,
+                     max_m: int = 8192) -> dict:
+        """Closed-loop saturation run: `outstanding` requests kept in the server."""
+        rep = sg_serve_report()
+        check(lib().sg_serve_closed(self.handle, outstanding, duration, warmup, seed, max_m,
+                                    ctypes.byref(rep)))
+        return {f: getattr(rep, f) for f, _ in sg_serve_report._fields_}
+
     def close(self):
         if getattr(self, "handle", None) and self.handle.value and _lib is not None:
-            _lib.sg_server_destroy(self.handle)
-            self.handle = ctypes.c_void_p(0)
+            h, self.handle = self.handle, ctypes.c_void_p(0)
+            check(_lib.sg_server_destroy(h))
 
     def __del__(self):
-        self.close()
+        if _live():
+            self.close()
 
 
 def gemm_batch(ctx: "Context", probs, c_dtype: int = BF16, mode: int = MODE_PLAIN, variant: int = 0,
@@ -621,12 +671,21 @@ def gemm_batch(ctx: "Context", probs, c_dtype: int = BF16, mode: int = MODE_PLAI
     check(lib().sg_gemm_batch(ctx.handle, len(arr), arr, c_dtype, mode, variant, _stream_ptr(stream)))
 
 
-def gemm_grouped(ctx: "Context", probs, c_dtype: int = BF16, tile: int = 3, stream=None):
-    """One-shot grouped launch (plan, launch, wait, free)."""
+def gemm_grouped(ctx: "Context", probs, c_dtype: int = BF16, tile: Optional[int] = 3, stream=None):
+    """One-shot grouped launch (plan, launch, wait, free); tile None autotunes the schedule."""
     arr = _problems(probs)
-    cfg = sg_group_cfg(tile, 0, 0)
-    check(lib().sg_gemm_grouped(ctx.handle, len(probs), arr, c_dtype, ctypes.byref(cfg),
-                                _stream_ptr(stream)))
+    cfg = None if tile is None else ctypes.byref(sg_group_cfg(tile, 0, 0))
+    check(lib().sg_gemm_grouped(ctx.handle, len(probs), arr, c_dtype, cfg, _stream_ptr(stream)))
+
+
+def set_default_table(device: int, table: Optional["Table"]):
+    """Lend `table` to the device's default context: gemm_bf16_nn then runs its DP plans.
+    The binding keeps a reference so the table outlives its use (None clears)."""
+    _default_tables[device] = table
+    check(lib().sg_set_default_table(device, table.handle if table else None))
+
+
+_default_tables = {}
 
 
 def noalloc_scratch_bytes() -> int:

@@ -99,6 +99,115 @@ __global__ __launch_bounds__(256) void sg_gemm_tile(KArgs p) {
     tile_body<BM, BN>(p, m0, n0, blockIdx.z, smem);
 }
 
+// ---- stream-K: the K iterations of all tiles shared evenly by the resident work-groups ------
+//
+// The launch's work is the list of (tile, K stage) iterations, tile-major (tiles M-fastest, the
+// stages of a tile in K order).  Work-group g of G takes iterations [g T / G, (g + 1) T / G) of
+// the T in total, so every work-group does the same amount of MFMA work whatever the tile count
+// (no wave-quantization tail).  A tile whose stages all fall to one work-group is written to C
+// directly; the other tiles are split between consecutive work-groups, each writing its FP32
+// partial of the tile to a slot of the workspace (slot 2 g for the first tile of g's range, 2 g + 1
+// for its last), and a fix-up kernel sums a split tile's partials in work-group order (so in K
+// order: bit-reproducible) and applies the epilogue.  Work-group g is the logical index of the
+// dispatch order remapped so that consecutive logical work-groups -- which share tiles and
+// operand panels -- run on one XCD.
+struct SkArgs {
+    float* partial;     // 2 G slots of BM x BN FP32, tile-local rows of BN
+    int tiles;          // tiles_m * tiles_n (data tiles)
+    int ipt;            // K stages per tile
+};
+
+__device__ __forceinline__ int sk_logical(int b, int G) {
+    const int x = b & 7, q = G >> 3, r = G & 7;
+    return x * q + (x < r ? x : r) + (b >> 3);
+}
+
+template <int BM, int BN>
+__global__ __launch_bounds__(256) void sg_gemm_tile_dma_sk(KArgs p, SkArgs s) {
+    __shared__ __attribute__((aligned(1024))) uint16_t smem[dma_smem_bytes<BM, BN>() / 2];
+    constexpr int BKD = DmaTile<BM, BN>::BKD;
+    const int G = gridDim.x;
+    const int g = sk_logical(blockIdx.x, G);
+    const int64_t total = (int64_t)s.tiles * s.ipt;
+    const int64_t begin = (int64_t)g * total / G, end = (int64_t)(g + 1) * total / G;
+    for (int64_t it = begin; it < end;) {
+        const int t = (int)(it / s.ipt);
+        const int k0 = (int)(it - (int64_t)t * s.ipt);
+        const int k1 = (int)min<int64_t>(s.ipt, k0 + (end - it));
+        const int m0 = (t % p.tiles_m) * BM, n0 = (t / p.tiles_m) * BN;
+        if (it != begin) __syncthreads();       // the previous segment is done with the LDS
+        // a whole tile goes to C; a partial goes to this work-group's slot, addressed as rows of
+        // BN from (m0, n0) (one tile body for both, its output arguments selected)
+        const bool whole = (k0 == 0 && k1 == s.ipt);
+        KArgs q = p;
+        if (!whole) {
+            const int slot = (it == begin) ? 2 * g : 2 * g + 1;
+            q.C = s.partial + (int64_t)slot * BM * BN - ((int64_t)m0 * BN + n0);
+            q.ldc = BN; q.out_bf16 = 0;
+            q.add = nullptr; q.add_kind = ADD_NONE; q.vec_ok = 1;
+        }
+        tile_body_dma_range<BM, BN>(q, m0, n0, 0, k0 * BKD, min(p.Kl, k1 * BKD), smem);
+        it += k1 - k0;
+    }
+}
+
+// Fix-up of a stream-K launch: one work-group per tile; a tile whose stages span work-groups
+// g_lo .. g_hi gets the sum of their partials (g ascending), plus the addend, stored to C.
+template <int BM, int BN>
+__global__ __launch_bounds__(256) void sg_sk_fixup(KArgs p, SkArgs s, int G) {
+    const int t = blockIdx.x;
+    const int64_t total = (int64_t)s.tiles * s.ipt;
+    // the work-group whose range holds iteration i: the last g with g T / G <= i
+    auto wg_of = [&](int64_t i) { return (int)(((i + 1) * G + total - 1) / total) - 1; };
+    const int64_t lo = (int64_t)t * s.ipt;
+    const int g_lo = wg_of(lo), g_hi = wg_of(lo + s.ipt - 1);
+    if (g_lo == g_hi) return;                   // written whole by one work-group
+    const int m0 = (t % p.tiles_m) * BM, n0 = (t / p.tiles_m) * BN;
+    constexpr int C4 = BN / 4;
+    for (int q = threadIdx.x; q < BM * C4; q += 256) {
+        const int r = q / C4, c = (q - r * C4) * 4;
+        const int m = m0 + r, n = n0 + c;
+        if (m >= p.M || n >= p.N) continue;
+        f32x4_t v = {0.f, 0.f, 0.f, 0.f};
+        for (int g = g_lo; g <= g_hi; ++g) {
+            const int64_t gb = (int64_t)g * total / G;
+            if (gb == (int64_t)(g + 1) * total / G) continue;      // empty range
+            const int slot = (gb / s.ipt == t) ? 2 * g : 2 * g + 1;
+            v += *(const f32x4_t*)(s.partial + (int64_t)slot * BM * BN + r * BN + c);
+        }
+        const bool full = p.vec_ok && (n + 3 < p.N);
+        if (p.add_kind == ADD_F32) {
+            const float* ap = (const float*)p.add + (int64_t)m * p.ldadd + n;
+            for (int e = 0; e < 4; ++e)
+                if (n + e < p.N) v[e] += ap[e];
+        } else if (p.add_kind == ADD_BF16) {
+            const uint16_t* ap = (const uint16_t*)p.add + (int64_t)m * p.ldadd + n;
+            for (int e = 0; e < 4; ++e)
+                if (n + e < p.N) v[e] += bf16_to_f32(ap[e]);
+        }
+        if (p.out_bf16) {
+            uint16_t* cp = (uint16_t*)p.C + (int64_t)m * p.ldc + n;
+            if (full) {
+                u32x2_t o;
+                o[0] = (uint32_t)f32_to_bf16_rne(v[0]) | ((uint32_t)f32_to_bf16_rne(v[1]) << 16);
+                o[1] = (uint32_t)f32_to_bf16_rne(v[2]) | ((uint32_t)f32_to_bf16_rne(v[3]) << 16);
+                *(u32x2_t*)cp = o;
+            } else {
+                for (int e = 0; e < 4; ++e)
+                    if (n + e < p.N) cp[e] = f32_to_bf16_rne(v[e]);
+            }
+        } else {
+            float* cp = (float*)p.C + (int64_t)m * p.ldc + n;
+            if (full) {
+                *(f32x4_t*)cp = v;
+            } else {
+                for (int e = 0; e < 4; ++e)
+                    if (n + e < p.N) cp[e] = v[e];
+            }
+        }
+    }
+}
+
 // Fixed-order sum of S FP32 partial slices (M x N, ld = N) plus the epilogue.
 __global__ __launch_bounds__(256) void sg_splitk_reduce(const float* ws, int64_t slice, int S,
                                                          int M, int N, void* C, int64_t ldc,
@@ -216,12 +325,90 @@ static bool in_place_b(const LaunchDesc& d) {
     return d.ldb % 8 == 0 && d.N % 8 == 0 && (uintptr_t)d.B % 16 == 0;
 }
 
+// Geometry of a stream-K launch of tile t: data tiles, K stages per tile, resident work-groups
+// G (occupancy on every CU, at most one per iteration) and whether any tile is split between
+// work-groups (then the fix-up runs).
+struct SkGeom {
+    int tiles = 0, ipt = 0, G = 0;
+    bool fixup = false;
+};
+
+template <int BM, int BN>
+static int sk_occupancy() {
+    static int occ = -1;
+    if (occ < 0) {
+        int o = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, sg_gemm_tile_dma_sk<BM, BN>, 256, 0) != hipSuccess || o < 1) {
+            (void)hipGetLastError();
+            o = 1;
+        }
+        occ = o;
+    }
+    return occ;
+}
+
+static int sk_occupancy_of(int tile) {
+    switch (tile) {
+        case 0: return sk_occupancy<256, 256>();
+        case 1: return sk_occupancy<256, 128>();
+        case 2: return sk_occupancy<128, 256>();
+        case 3: return sk_occupancy<128, 128>();
+        case 4: return sk_occupancy<128, 64>();
+        case 5: return sk_occupancy<64, 128>();
+        default: return sk_occupancy<64, 64>();
+    }
+}
+
+static int device_cus() {
+    static int cus[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    if (cus[dev] == 0) {
+        int c = 0;
+        if (hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || c < 1) c = 256;
+        cus[dev] = c;
+    }
+    return cus[dev];
+}
+
+static int stage_depth_of(int tile) {
+    switch (tile) {
+        case 0: return DmaTile<256, 256>::BKD;
+        case 1: return DmaTile<256, 128>::BKD;
+        case 2: return DmaTile<128, 256>::BKD;
+        case 3: return DmaTile<128, 128>::BKD;
+        case 4: return DmaTile<128, 64>::BKD;
+        case 5: return DmaTile<64, 128>::BKD;
+        case 6: return DmaTile<64, 64>::BKD;
+        default: return DmaTile<64, 64, true>::BKD;
+    }
+}
+
+static SkGeom sk_geometry(int variant, const LaunchDesc& d) {
+    SkGeom g;
+    const int tile = variant_tile(variant);
+    const TileShape ts = kTiles[tile];
+    const int bkd = stage_depth_of(tile);
+    g.tiles = (int)(((d.M + ts.bm - 1) / ts.bm) * ((d.N + ts.bn - 1) / ts.bn));
+    g.ipt = (int)((d.Kl + bkd - 1) / bkd);
+    const int64_t total = (int64_t)g.tiles * g.ipt;
+    g.G = (int)std::min<int64_t>(total, (int64_t)sk_occupancy_of(tile) * device_cus());
+    if (g.G < 1) g.G = 1;
+    for (int64_t w = 1; w < g.G && !g.fixup; ++w)
+        if ((w * total / g.G) % g.ipt != 0) g.fixup = true;     // a range boundary inside a tile
+    return g;
+}
+
 static Packing packing_of(int variant, const LaunchDesc& d) {
     Packing pk;
     int S;
     int64_t kc;
     split_geometry(variant, d.Kl, &S, &kc);
     pk.part_bytes = S > 1 ? round256((size_t)S * (size_t)d.M * (size_t)d.N * sizeof(float)) : 0;
+    if (variant_is_sk(variant)) {
+        const TileShape ts = kTiles[variant_tile(variant)];
+        pk.part_bytes = round256((size_t)2 * sk_geometry(variant, d).G * ts.bm * ts.bn * sizeof(float));
+    }
     pk.total = pk.part_bytes;
     if (d.K <= 0 || (in_place_a(d) && in_place_b(d))) return pk;
     pk.k8 = (d.K + 7) / 8 * 8;
@@ -278,8 +465,87 @@ static int twin_extra_lds() {
     return -1;
 }
 
+// Whether the direct-to-LDS body can run the launch: operands aligned in place, or packed into
+// the workspace, with every byte offset inside the loads' 31-bit range.
+static bool dma_feasible(int variant, const LaunchDesc& d, bool have_ws) {
+    const Packing pk = packing_of(variant, d);
+    const bool packed = (pk.pack_a || pk.pack_b) && have_ws;
+    const int64_t a_bytes = pk.pack_a && packed ? d.M * pk.k8 * 2 : ((d.M - 1) * d.lda + d.K) * 2;
+    const int64_t b_bytes = d.K <= 0 ? 0 : pk.pack_b && packed ? d.K * pk.n8 * 2 : ((d.K - 1) * d.ldb + d.N) * 2;
+    return (packed || (in_place_a(d) && in_place_b(d))) && a_bytes < 0x7FFFFFFF && b_bytes < 0x7FFFFFFF;
+}
+
+bool launch_has_second_kernel(int variant, const LaunchDesc& d) {
+    if (variant_is_sk(variant))
+        return dma_feasible(variant, d, true) && !d.mem_only && sk_geometry(variant, d).fixup;
+    int S = 1;
+    int64_t kc = 0;
+    split_geometry(variant, d.Kl, &S, &kc);
+    return S > 1;
+}
+
 template <int BM, int BN, bool DEEP = false>
+static int launch_tile(const LaunchDesc& d, int variant, void* ws, hipStream_t stream);
+
+// A stream-K launch: operand packing as for the other variants, the stream-K tile kernel over
+// the data tiles, and the fix-up when a tile is split between work-groups.  Operands the
+// direct-to-LDS body cannot load run the tile's plain (one-split) variant instead.
+template <int BM, int BN>
+static int launch_sk(const LaunchDesc& d, int variant, void* ws, hipStream_t stream) {
+    if (d.mem_only) return fail(SG_EINVAL, "stream-K variants have no memory-only twin");
+    if (ws == nullptr) return fail(SG_EINVAL, "stream-K launch without workspace");
+    const int tile = variant_tile(variant);
+    if (!dma_feasible(variant, d, true)) return launch_tile<BM, BN>(d, tile * kSplitLevels, ws, stream);
+    const Packing pk = packing_of(variant, d);
+    const SkGeom gm = sk_geometry(variant, d);
+    KArgs a;
+    a.A = d.A; a.B = d.B;
+    a.lda = d.lda; a.ldb = d.ldb;
+    hipEvent_t start = d.ev_start;
+    if (pk.pack_a) {
+        uint16_t* ap = (uint16_t*)((char*)ws + pk.a_off);
+        int rc = launch_pack(d.A, d.lda, d.M, d.K, ap, pk.k8, start, stream);
+        if (rc) return rc;
+        start = nullptr;
+        a.A = ap; a.lda = pk.k8;
+    }
+    if (pk.pack_b) {
+        uint16_t* bp = (uint16_t*)((char*)ws + pk.b_off);
+        int rc = launch_pack(d.B, d.ldb, d.K, d.N, bp, pk.n8, start, stream);
+        if (rc) return rc;
+        start = nullptr;
+        a.B = bp; a.ldb = pk.n8;
+    }
+    a.a_bytes = (int)(pk.pack_a ? d.M * pk.k8 * 2 : ((d.M - 1) * d.lda + d.K) * 2);
+    a.b_bytes = (int)(pk.pack_b ? d.K * pk.n8 * 2 : ((d.K - 1) * d.ldb + d.N) * 2);
+    a.M = (int)d.M; a.N = (int)d.N; a.K = (int)d.K; a.Kl = (int)d.Kl;
+    a.tiles_m = (int)((d.M + BM - 1) / BM);
+    a.tiles_n = (int)((d.N + BN - 1) / BN);
+    a.k_chunk = (int)d.Kl;
+    a.C = d.C; a.ldc = d.ldc; a.ws_slice = 0;
+    a.out_bf16 = d.out_bf16; a.add = d.add; a.ldadd = d.ldadd; a.add_kind = d.add_kind;
+    const size_t esz = d.out_bf16 ? 2 : 4;
+    bool vec_c = (d.ldc % 4 == 0) && ((uintptr_t)d.C % (4 * esz) == 0);
+    if (d.add_kind == ADD_F32) vec_c = vec_c && (d.ldadd % 4 == 0) && ((uintptr_t)d.add % 16 == 0);
+    if (d.add_kind == ADD_BF16) vec_c = vec_c && (d.ldadd % 4 == 0) && ((uintptr_t)d.add % 8 == 0);
+    a.vec_ok = vec_c ? 1 : 0;
+    if (gm.tiles <= 0) return SG_OK;
+    const SkArgs sk{(float*)ws, gm.tiles, gm.ipt};
+    hipExtLaunchKernelGGL(sg_gemm_tile_dma_sk<BM, BN>, dim3((unsigned)gm.G), dim3(256), 0, stream, start,
+                          gm.fixup ? d.ev_mid : d.ev_stop, 0, a, sk);
+    SG_HIP(hipGetLastError());
+    if (gm.fixup) {
+        hipExtLaunchKernelGGL(sg_sk_fixup<BM, BN>, dim3((unsigned)gm.tiles), dim3(256), 0, stream, nullptr,
+                              d.ev_stop, 0, a, sk, gm.G);
+        SG_HIP(hipGetLastError());
+    }
+    return SG_OK;
+}
+
+template <int BM, int BN, bool DEEP>
 static int launch_tile(const LaunchDesc& d, int variant, void* ws, hipStream_t stream) {
+    if constexpr (!DEEP)
+        if (variant_is_sk(variant)) return launch_sk<BM, BN>(d, variant, ws, stream);
     KArgs a;
     a.A = d.A; a.B = d.B;
     a.lda = d.lda; a.ldb = d.ldb;

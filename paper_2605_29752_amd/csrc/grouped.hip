@@ -14,6 +14,7 @@
 #include <numeric>
 
 #include "sg_internal.h"
+#include "sg_table.h"
 #include "tile_body.h"
 #include "tile_body_dma.h"
 
@@ -205,6 +206,102 @@ int plan_enqueue(sg_group_plan* pl, hipStream_t s, hipEvent_t start = nullptr, h
                            pl->c_dtype, pl->d_counters, s, start, stop);
 }
 
+// Key of a group's schedule in the table: the problem list in the caller's order (dimensions,
+// and the alignment classes that choose the kernel body and the store width) and c_dtype.
+uint64_t group_key(const sg_problem* probs, int G, int c_dtype) {
+    uint64_t h = 0xcbf29ce484222325ull;
+    auto mix = [&](uint64_t v) {
+        h ^= v + 0x9E3779B97F4A7C15ull + (h << 6) + (h >> 2);
+        h *= 0x100000001b3ull;
+    };
+    mix((uint64_t)G);
+    mix((uint64_t)c_dtype);
+    for (int i = 0; i < G; ++i) {
+        const sg_problem& q = probs[i];
+        mix((uint64_t)q.M);
+        mix((uint64_t)q.N);
+        mix((uint64_t)q.K);
+        const uint64_t cls = (uint64_t)(q.lda % 8 == 0) | ((uint64_t)(q.ldb % 8 == 0) << 1) |
+                             ((uint64_t)((uintptr_t)q.A % 16 == 0) << 2) |
+                             ((uint64_t)((uintptr_t)q.B % 16 == 0) << 3) | ((uint64_t)(q.ldc % 4 == 0) << 4) |
+                             ((uint64_t)((uintptr_t)q.C % 16 == 0) << 5);
+        mix(cls);
+    }
+    return h;
+}
+
+// Time one configuration: upload its descriptors, one warm-up launch, best of three.
+int time_config(sg_group_plan* pl, const sg_problem* probs, const sg_group_cfg& c, hipStream_t s,
+                hipEvent_t e0, hipEvent_t e1, double* sec) {
+    pl->cfg = c;
+    int rc = plan_upload(pl, probs, s);
+    if (rc) return rc;
+    rc = plan_enqueue(pl, s);
+    if (rc) return rc;
+    double best = INFINITY;
+    for (int r = 0; r < 3; ++r) {
+        rc = plan_enqueue(pl, s, e0, e1);
+        if (rc) return rc;
+        SG_HIP(hipEventSynchronize(e1));
+        float ms = 0.f;
+        SG_HIP(hipEventElapsedTime(&ms, e0, e1));
+        best = std::min(best, (double)ms * 1e-3);
+    }
+    *sec = best;
+    return SG_OK;
+}
+
+// Autotune a group's schedule: every tile shape at full residency with the longest-K-first
+// queue, then, for the two fastest tiles, the queue in the caller's order and smaller grids
+// (one work-group per CU, and half the resident count), so that fewer, fuller work-groups can
+// win where the tail of the queue is short.  The winner is left in pl->cfg (descriptors
+// uploaded); *sec receives its time.
+int autotune(sg_group_plan* pl, const sg_problem* probs, hipStream_t s, double* sec) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    SG_HIP(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(SG_EHIP, "grouped: event creation failed");
+    }
+    int cus = 0;
+    int rc = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, pl->device) == hipSuccess
+                 ? SG_OK : fail(SG_EHIP, "grouped: device query failed");
+    std::vector<std::pair<double, sg_group_cfg>> tried;
+    for (int t = 0; t < kNumGroupTiles && rc == SG_OK; ++t) {
+        double x = 0;
+        const sg_group_cfg c{t, 0, 0};
+        rc = time_config(pl, probs, c, s, e0, e1, &x);
+        if (rc == SG_OK) tried.emplace_back(x, c);
+    }
+    if (rc == SG_OK) {
+        std::sort(tried.begin(), tried.end(), [](const auto& a, const auto& b) { return a.first < b.first; });
+        const size_t top = std::min<size_t>(2, tried.size());
+        for (size_t i = 0; i < top && rc == SG_OK; ++i) {
+            const int t = tried[i].second.tile;
+            int full = 0;
+            rc = grouped_grid(t, pl->all_aligned, pl->device, INT32_MAX, 0, &full);
+            if (rc) break;
+            std::vector<sg_group_cfg> more{{t, 0, 1}};
+            if (full > cus) more.push_back({t, cus, 0});
+            if (full > 2 * cus) more.push_back({t, (full / cus / 2) * cus, 0});
+            for (const sg_group_cfg& c : more) {
+                double x = 0;
+                rc = time_config(pl, probs, c, s, e0, e1, &x);
+                if (rc) break;
+                tried.emplace_back(x, c);
+            }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    const auto best = *std::min_element(tried.begin(), tried.end(),
+                                        [](const auto& a, const auto& b) { return a.first < b.first; });
+    pl->cfg = best.second;
+    *sec = best.first;
+    return plan_upload(pl, probs, s);
+}
+
 }  // namespace
 
 extern "C" {
@@ -239,36 +336,28 @@ int sg_group_plan_create(sg_ctx* ctx, int G, const sg_problem* probs, int c_dtyp
         pl->cfg = *cfg;
         rc = plan_upload(pl, probs, s);
     } else {
-        // autotune: every tile shape of the family, longest-K-first queue, best of 3 timed runs
-        hipEvent_t e0, e1;
-        SG_HIP(hipEventCreate(&e0));
-        SG_HIP(hipEventCreate(&e1));
-        double best = INFINITY;
-        sg_group_cfg best_cfg{3, 0, 0};
-        for (int t = 0; t < kNumGroupTiles && rc == SG_OK; ++t) {
-            pl->cfg = sg_group_cfg{t, 0, 0};
-            rc = plan_upload(pl, probs, s);
-            if (rc) break;
-            rc = plan_enqueue(pl, s);                         // warm-up
-            double tmin = INFINITY;
-            for (int r = 0; r < 3 && rc == SG_OK; ++r) {
-                rc = plan_enqueue(pl, s, e0, e1);
-                if (rc) break;
-                if (hipEventSynchronize(e1) != hipSuccess) { rc = fail(SG_EHIP, "grouped: timing failed"); break; }
-                float ms = 0.f;
-                (void)hipEventElapsedTime(&ms, e0, e1);
-                tmin = std::min(tmin, (double)ms);
-            }
-            if (rc == SG_OK && tmin < best) {
-                best = tmin;
-                best_cfg = pl->cfg;
+        // a schedule recorded in the context's table for this very group is taken by lookup;
+        // otherwise the autotuner times candidates and records its winner there
+        const sg_table* tab = ctx_table(ctx);
+        const uint64_t key = group_key(probs, G, c_dtype);
+        bool hit = false;
+        if (tab) {
+            std::lock_guard<std::mutex> lk(tab->group_mu);
+            auto it = tab->group_sched.find(key);
+            if (it != tab->group_sched.end()) {
+                pl->cfg = sg_group_cfg{it->second.tile, it->second.grid_wgs, it->second.order};
+                hit = true;
             }
         }
-        (void)hipEventDestroy(e0);
-        (void)hipEventDestroy(e1);
-        if (rc == SG_OK) {
-            pl->cfg = best_cfg;
+        if (hit) {
             rc = plan_upload(pl, probs, s);
+        } else {
+            double sec = 0.0;
+            rc = autotune(pl, probs, s, &sec);
+            if (rc == SG_OK && tab) {
+                std::lock_guard<std::mutex> lk(tab->group_mu);
+                tab->group_sched[key] = sg_table::GroupSched{pl->cfg.tile, pl->cfg.grid_wgs, pl->cfg.order, sec};
+            }
         }
     }
     if (rc) {
@@ -289,11 +378,13 @@ int sg_group_plan_update(sg_group_plan* pl, const sg_problem* probs, void* strea
     int rc = validate_problems(pl->G, probs);
     if (rc) return rc;
     const int old_tiles = pl->total_tiles, old_grid = pl->grid;
+    const bool old_aligned = pl->all_aligned;
     rc = plan_upload(pl, probs, (hipStream_t)stream);
     if (rc) return rc;
-    if (pl->total_tiles != old_tiles || pl->grid != old_grid) {
-        // a captured graph bakes in the launch arguments: signal that it must be recaptured
-        return fail(SG_EAGAIN, "grouped: tile count changed; recapture graphs that hold this plan");
+    if (pl->total_tiles != old_tiles || pl->grid != old_grid || pl->all_aligned != old_aligned) {
+        // a captured graph bakes in the launch arguments and the kernel (the all-aligned one
+        // carries no element-wise body): signal that it must be recaptured
+        return fail(SG_EAGAIN, "grouped: tile count, grid or kernel changed; recapture graphs that hold this plan");
     }
     return SG_OK;
 }
@@ -309,18 +400,25 @@ int sg_group_plan_info(const sg_group_plan* pl, sg_group_cfg* cfg, int* total_ti
 
 int sg_group_plan_destroy(sg_group_plan* pl) {
     if (!pl) return SG_OK;
-    (void)hipDeviceSynchronize();
-    if (pl->d_probs) (void)hipFree(pl->d_probs);
-    if (pl->d_counters) (void)hipFree(pl->d_counters);
+    // every resource is released even after a failure; the first HIP error is reported
+    hipError_t first = hipDeviceSynchronize();
+    const char* what = "hipDeviceSynchronize";
+    if (pl->d_probs) {
+        const hipError_t e = hipFree(pl->d_probs);
+        if (first == hipSuccess && e != hipSuccess) { first = e; what = "hipFree"; }
+    }
+    if (pl->d_counters) {
+        const hipError_t e = hipFree(pl->d_counters);
+        if (first == hipSuccess && e != hipSuccess) { first = e; what = "hipFree"; }
+    }
     delete pl;
-    return SG_OK;
+    return first == hipSuccess ? SG_OK : hip_fail(first, what);
 }
 
 int sg_gemm_grouped(sg_ctx* ctx, int G, const sg_problem* probs, int c_dtype, const sg_group_cfg* cfg,
                     void* stream) {
     sg_group_plan* pl = nullptr;
-    sg_group_cfg def{3, 0, 0};
-    int rc = sg_group_plan_create(ctx, G, probs, c_dtype, cfg ? cfg : &def, stream, &pl);
+    int rc = sg_group_plan_create(ctx, G, probs, c_dtype, cfg, stream, &pl);
     if (rc) return rc;
     rc = plan_enqueue(pl, (hipStream_t)stream);
     if (rc == SG_OK && hipStreamSynchronize((hipStream_t)stream) != hipSuccess) rc = fail(SG_EHIP, "grouped: sync failed");
@@ -365,10 +463,14 @@ int sg_graph_launch(sg_graph* g, void* stream) {
 
 int sg_graph_destroy(sg_graph* g) {
     if (!g) return SG_OK;
-    if (g->exec) (void)hipGraphExecDestroy(g->exec);
-    if (g->graph) (void)hipGraphDestroy(g->graph);
+    hipError_t first = hipSuccess;
+    if (g->exec) first = hipGraphExecDestroy(g->exec);
+    if (g->graph) {
+        const hipError_t e = hipGraphDestroy(g->graph);
+        if (first == hipSuccess) first = e;
+    }
     delete g;
-    return SG_OK;
+    return first == hipSuccess ? SG_OK : hip_fail(first, "graph destroy");
 }
 
 }  // extern "C"

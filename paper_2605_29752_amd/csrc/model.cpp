@@ -40,6 +40,18 @@ double roughness_n(const double* T, int nm, int nn, int nk) {
     return s / ((double)nm * nk);
 }
 
+// Channel share of a tensor moved in rows of 256 elements (Sec. 9.2): the address space is
+// striped over `channels` channels in `interleave`-byte blocks; a row spans
+// w = min(channels, 256 e / interleave) channels and row starts advance by
+// s = (L e / interleave) mod channels blocks, reaching channels / gcd(s, channels) of them.
+double channel_share(int64_t L, int e, int channels, int interleave) {
+    const int64_t w = std::min<int64_t>(channels, std::max<int64_t>(1, (256 * (int64_t)e) / interleave));
+    const int64_t s = ((L * e) / interleave) % channels;
+    int64_t a = s, b = channels;
+    while (b) { const int64_t t = a % b; a = b; b = t; }      // gcd(s, channels)
+    return (double)std::min<int64_t>(channels, w * channels / a) / channels;
+}
+
 int throughput_band(double tau) { return tau >= 0.95 ? 3 : tau >= 0.75 ? 2 : tau >= 0.50 ? 1 : 0; }
 int smoothness_band(double rho) { return rho <= 1.25 ? 3 : rho <= 2.0 ? 2 : rho <= 3.0 ? 1 : 0; }
 
@@ -62,7 +74,13 @@ int sg_ideal_landscape(const sg_grid* g, const sg_hw* hw, int tile, double* out)
 
 int sg_optimal_landscape(const sg_grid* g, const sg_hw* hw, const int* tiles, int ntiles, int c_bytes,
                          double* out) {
-    if (!grid_ok(g) || !hw_ok(hw) || !tiles || ntiles <= 0 || c_bytes <= 0 || !out)
+    return sg_optimal_landscape_ch(g, hw, tiles, ntiles, c_bytes, 0, 256, out);
+}
+
+int sg_optimal_landscape_ch(const sg_grid* g, const sg_hw* hw, const int* tiles, int ntiles, int c_bytes,
+                            int channels, int interleave, double* out) {
+    if (!grid_ok(g) || !hw_ok(hw) || !tiles || ntiles <= 0 || c_bytes <= 0 || !out || channels < 0 ||
+        (channels > 0 && interleave <= 0))
         return sg::fail(SG_EINVAL, "sg_optimal_landscape: bad argument");
     for (int t = 0; t < ntiles; ++t)
         if (tiles[t] <= 0) return sg::fail(SG_EINVAL, "sg_optimal_landscape: tile edge must be positive");
@@ -74,7 +92,13 @@ int sg_optimal_landscape(const sg_grid* g, const sg_hw* hw, const int* tiles, in
                 const double M = (double)(a + 1) * g->step, N = (double)(b + 1) * g->step;
                 const double K = (double)(c + 1) * g->step;
                 const double flop = 2.0 * M * N * K;
-                const double t_mem = (2.0 * M * K + 2.0 * K * N + (double)c_bytes * M * N) / bw;
+                double ea = 1.0, eb = 1.0, ed = 1.0;
+                if (channels > 0) {
+                    ea = channel_share((int64_t)K, 2, channels, interleave);
+                    eb = channel_share((int64_t)N, 2, channels, interleave);
+                    ed = channel_share((int64_t)N, c_bytes, channels, interleave);
+                }
+                const double t_mem = (2.0 * M * K / ea + 2.0 * K * N / eb + (double)c_bytes * M * N / ed) / bw;
                 double best = std::numeric_limits<double>::infinity();
                 for (int t = 0; t < ntiles; ++t) {
                     const double t_comp = flop / (peak * wave_efficiency(M, N, tiles[t], hw->cores));

@@ -47,6 +47,10 @@ struct sg_ctx {
     std::vector<int64_t> acct_launches;
     std::vector<double> acct_seconds;
     std::vector<double> acct_flops;
+    // interval timing: sweeps also time each run between two markers on the caller's stream
+    // (launch and inter-kernel gaps included); per-shape means of the most recent sweep
+    int interval_timing = 0;
+    std::vector<double> interval_sec;
 };
 
 namespace {
@@ -234,14 +238,10 @@ size_t plan_workspace_concurrent(const Problem& pr, const std::vector<Leaf>& lea
     return total;
 }
 
-// Enqueue one leaf.  Output routing (C FP32: accumulate in place; C BF16 with a K split:
-// accumulate in the FP32 plan accumulator W and round once in the last piece).
-int run_leaf(const Problem& pr, const Leaf& L, void* ws, size_t acc_bytes, hipStream_t s,
-             hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr, hipEvent_t ev_mid = nullptr) {
+// Launch description of one leaf.  Output routing (C FP32: accumulate in place; C BF16 with a
+// K split: accumulate in the FP32 plan accumulator W and round once in the last piece).
+LaunchDesc leaf_desc(const Problem& pr, const Leaf& L, void* ws) {
     LaunchDesc d{};
-    d.ev_start = ev_start;
-    d.ev_mid = ev_mid;
-    d.ev_stop = ev_stop;
     d.mem_only = pr.mem_only;
     d.M = L.m; d.N = L.n; d.K = L.k; d.Ml = L.Ml; d.Nl = L.Nl; d.Kl = L.Kl;
     d.A = pr.A + L.m0 * pr.lda + L.k0; d.lda = pr.lda;
@@ -268,6 +268,16 @@ int run_leaf(const Problem& pr, const Leaf& L, void* ws, size_t acc_bytes, hipSt
         d.C = (uint16_t*)pr.C + coff; d.ldc = pr.ldc; d.out_bf16 = 1;
         d.add = W + woff; d.ldadd = pr.N; d.add_kind = ADD_F32;
     }
+    return d;
+}
+
+// Enqueue one leaf; the events (may be null) are stamped as LaunchDesc describes.
+int run_leaf(const Problem& pr, const Leaf& L, void* ws, size_t acc_bytes, hipStream_t s,
+             hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr, hipEvent_t ev_mid = nullptr) {
+    LaunchDesc d = leaf_desc(pr, L, ws);
+    d.ev_start = ev_start;
+    d.ev_mid = ev_mid;
+    d.ev_stop = ev_stop;
     return launch_variant(L.variant, d, (char*)ws + acc_bytes, s);
 }
 
@@ -426,6 +436,10 @@ void* scratch_of(int device) {
 
 }  // namespace
 
+namespace sg {
+const sg_table* ctx_table(const sg_ctx* ctx) { return ctx ? ctx->table : nullptr; }
+}  // namespace sg
+
 extern "C" {
 
 const char* sg_last_error(void) { return g_err.c_str(); }
@@ -458,18 +472,30 @@ int sg_ctx_create(int device, sg_ctx** out) {
 
 int sg_ctx_destroy(sg_ctx* ctx) {
     if (!ctx) return SG_OK;
-    DeviceGuard guard(ctx->device);
-    for (hipStream_t st : ctx->aux) {
-        (void)hipStreamSynchronize(st);
-        (void)hipStreamDestroy(st);
+    {
+        std::lock_guard<std::mutex> lk(g_default_mu);
+        for (sg_ctx*& d : g_default)
+            if (d == ctx) d = nullptr;              // a destroyed default context is recreated on use
     }
-    for (hipEvent_t e : ctx->events) (void)hipEventDestroy(e);
-    for (hipEvent_t e : ctx->marks) (void)hipEventDestroy(e);
+    DeviceGuard guard(ctx->device);
+    // every resource is released even after a failure; the first HIP error is reported
+    hipError_t first = hipSuccess;
+    const char* what = nullptr;
+    auto note = [&](hipError_t e, const char* w) {
+        if (e != hipSuccess && first == hipSuccess) { first = e; what = w; }
+    };
+    for (hipStream_t st : ctx->aux) {
+        note(hipStreamSynchronize(st), "hipStreamSynchronize");
+        note(hipStreamDestroy(st), "hipStreamDestroy");
+    }
+    for (hipEvent_t e : ctx->events) note(hipEventDestroy(e), "hipEventDestroy");
+    for (hipEvent_t e : ctx->marks) note(hipEventDestroy(e), "hipEventDestroy");
     if (ctx->ws) {
-        (void)hipDeviceSynchronize();
-        (void)hipFree(ctx->ws);
+        note(hipDeviceSynchronize(), "hipDeviceSynchronize");
+        note(hipFree(ctx->ws), "hipFree");
     }
     delete ctx;
+    if (first != hipSuccess) return hip_fail(first, what);
     return SG_OK;
 }
 
@@ -504,24 +530,48 @@ int sg_ctx_set_table(sg_ctx* ctx, const sg_table* t) {
     return SG_OK;
 }
 
+// The per-device default context of the paper-form call, created on first use.  Called with
+// g_default_mu held.
+static int default_ctx_locked(int dev, sg_ctx** out) {
+    if (dev < 0 || dev >= 64) return fail(SG_EINVAL, "device ordinal out of range");
+    if (!g_default[dev]) {
+        int n = 0;
+        SG_HIP(hipGetDeviceCount(&n));
+        if (dev >= n) return fail(SG_EINVAL, "no such device");
+        const int rc = sg_ctx_create(dev, &g_default[dev]);
+        if (rc) return rc;
+    }
+    *out = g_default[dev];
+    return SG_OK;
+}
+
+int sg_default_ctx(int device, sg_ctx** out) {
+    if (!out) return fail(SG_EINVAL, "NULL out");
+    std::lock_guard<std::mutex> lk(g_default_mu);
+    return default_ctx_locked(device, out);
+}
+
+int sg_set_default_table(int device, const sg_table* t) {
+    std::lock_guard<std::mutex> lk(g_default_mu);
+    sg_ctx* ctx = nullptr;
+    const int rc = default_ctx_locked(device, &ctx);
+    if (rc) return rc;
+    ctx->table = t;
+    return SG_OK;
+}
+
 int gemm_bf16_nn(int64_t M, int64_t N, int64_t K, const void* A, const void* B, void* C) {
     int dev = 0;
     SG_HIP(hipGetDevice(&dev));
-    if (dev < 0 || dev >= 64) return fail(SG_EINVAL, "device ordinal too large");
-    sg_ctx* ctx;
-    {
-        std::lock_guard<std::mutex> lk(g_default_mu);
-        if (!g_default[dev]) {
-            int rc = sg_ctx_create(dev, &g_default[dev]);
-            if (rc) return rc;
-        }
-        ctx = g_default[dev];
-    }
+    std::lock_guard<std::mutex> lk(g_default_mu);
+    sg_ctx* ctx = nullptr;
+    int rc = default_ctx_locked(dev, &ctx);
+    if (rc) return rc;
+    DeviceGuard guard(ctx->device);
     sg_gemm_args a{};
     a.M = M; a.N = N; a.K = K;
     a.A = A; a.lda = K; a.B = B; a.ldb = N; a.C = C; a.ldc = N;
     a.c_dtype = SG_F32; a.beta = 0; a.mode = SG_MODE_DEFAULT; a.variant = 0;
-    std::lock_guard<std::mutex> lk(g_default_mu);
     return gemm_impl(ctx, &a, nullptr);
 }
 
@@ -572,7 +622,12 @@ int sg_variant_info_get(int v, sg_variant_info* out) {
     out->splits = variant_splits(v);
     out->threads = 256;
     out->lds_bytes = lds_bytes_of_tile(variant_tile(v));
-    std::snprintf(out->name, sizeof out->name, "%dx%dx%d_s%d", t.bm, t.bn, out->bk, out->splits);
+    if (variant_is_sk(v)) {
+        out->splits = 0;
+        std::snprintf(out->name, sizeof out->name, "%dx%dx%d_sk", t.bm, t.bn, out->bk);
+    } else {
+        std::snprintf(out->name, sizeof out->name, "%dx%dx%d_s%d", t.bm, t.bn, out->bk, out->splits);
+    }
     return SG_OK;
 }
 
@@ -631,14 +686,11 @@ int sg_fill_bf16(void* dst, int64_t n, uint64_t seed, uint64_t stream, int64_t o
 // ---- sweep driver ----------------------------------------------------------------------------
 namespace sg {
 
-// Whether a leaf's launch is followed by a separate split-K reduction (and so stamps its mid
-// event): the splits that are not empty over the leaf's K extent, not the variant's nominal
-// count (a split-K variant on a short K runs as one split).
-bool stamps_mid(const Leaf& L) {
-    int S = 1;
-    int64_t kc = 0;
-    split_geometry(L.variant, L.Kl, &S, &kc);
-    return S > 1;
+// Whether a leaf's launch runs a second kernel after its tile kernel (a split-K reduction over
+// the splits that are not empty on the leaf's K extent, or a stream-K fix-up) and so stamps its
+// mid event.
+bool stamps_mid(const Problem& pr, const Leaf& L, void* ws) {
+    return launch_has_second_kernel(L.variant, leaf_desc(pr, L, ws));
 }
 
 // Time `reps` runs of the plan `leaves` (after one untimed run).  Every kernel launch carries
@@ -649,10 +701,16 @@ bool stamps_mid(const Leaf& L) {
 int time_plan_concurrent(sg_ctx* ctx, const Problem& pr, const std::vector<Leaf>& leaves, int reps,
                          hipStream_t s, double* sec, bool account);
 
+// interval != nullptr: `reps` further runs follow, each bracketed by two markers recorded on s
+// (from an event pool of their own) and carrying no per-dispatch timing events, and *interval
+// receives their mean marker-to-marker time (kernels plus the gaps between them).
 int time_plan(sg_ctx* ctx, const Problem& pr, const std::vector<Leaf>& leaves, int reps,
-              hipStream_t s, double* sec, bool account) {
-    if (ctx->concurrent_splits != 0 && plan_is_concurrent(leaves))
-        return time_plan_concurrent(ctx, pr, leaves, reps, s, sec, account);
+              hipStream_t s, double* sec, bool account, double* interval = nullptr) {
+    if (ctx->concurrent_splits != 0 && plan_is_concurrent(leaves)) {
+        const int rc = time_plan_concurrent(ctx, pr, leaves, reps, s, sec, account);
+        if (rc == SG_OK && interval) *interval = *sec;      // already a marker interval
+        return rc;
+    }
     size_t acc_bytes = 0;
     int rc = ensure_ws(ctx, plan_workspace(pr, leaves, &acc_bytes));
     if (rc) return rc;
@@ -665,20 +723,45 @@ int time_plan(sg_ctx* ctx, const Problem& pr, const std::vector<Leaf>& leaves, i
     rc = ensure_events(ctx, ne);
     if (rc) return rc;
     size_t e = 0;
-    for (int r = 0; r < reps; ++r)
+    for (int r = 0; r < reps; ++r) {
         for (const Leaf& L : leaves) {
-            const bool split = stamps_mid(L);
+            const bool split = stamps_mid(pr, L, ctx->ws);
             rc = run_leaf(pr, L, ctx->ws, acc_bytes, s, ctx->events[e], ctx->events[e + 1],
                           split ? ctx->events[e + 2] : nullptr);
             if (rc) return rc;
             e += 3;
         }
+    }
+    if (interval) {
+        // `reps` more runs, each between two markers and with no timing events of its own
+        // inside, so the interval holds the plan's kernels and the gaps between them only
+        rc = ensure_marks(ctx, 2 * (size_t)reps);
+        if (rc) return rc;
+        for (int r = 0; r < reps; ++r) {
+            SG_HIP(hipEventRecord(ctx->marks[2 * r], s));
+            for (const Leaf& L : leaves) {
+                rc = run_leaf(pr, L, ctx->ws, acc_bytes, s);
+                if (rc) return rc;
+            }
+            SG_HIP(hipEventRecord(ctx->marks[2 * r + 1], s));
+        }
+    }
     SG_HIP(hipEventSynchronize(ctx->events[ne - 2]));
+    if (interval) {
+        SG_HIP(hipEventSynchronize(ctx->marks[2 * reps - 1]));
+        double t = 0.0;
+        for (int r = 0; r < reps; ++r) {
+            float ms = 0.f;
+            SG_HIP(hipEventElapsedTime(&ms, ctx->marks[2 * r], ctx->marks[2 * r + 1]));
+            t += (double)ms * 1e-3;
+        }
+        *interval = t / reps;
+    }
     double total = 0.0;
     e = 0;
     for (int r = 0; r < reps; ++r)
         for (const Leaf& L : leaves) {
-            const bool split = stamps_mid(L);
+            const bool split = stamps_mid(pr, L, ctx->ws);
             float ms = 0.f, ms_kernel = 0.f;
             SG_HIP(hipEventElapsedTime(&ms, ctx->events[e], ctx->events[e + 1]));
             if (split) SG_HIP(hipEventElapsedTime(&ms_kernel, ctx->events[e], ctx->events[e + 2]));
@@ -754,6 +837,7 @@ extern "C" int sg_sweep(sg_ctx* ctx, const sg_shape* shapes, int64_t n, int mode
     std::fill(ctx->acct_launches.begin(), ctx->acct_launches.end(), 0);
     std::fill(ctx->acct_seconds.begin(), ctx->acct_seconds.end(), 0.0);
     std::fill(ctx->acct_flops.begin(), ctx->acct_flops.end(), 0.0);
+    ctx->interval_sec.assign(ctx->interval_timing ? (size_t)n : 0, 0.0);
     std::vector<Leaf> leaves;
     for (int64_t i = 0; i < n; ++i) {
         const sg_shape& sh = shapes[i];
@@ -772,7 +856,8 @@ extern "C" int sg_sweep(sg_ctx* ctx, const sg_shape* shapes, int64_t n, int mode
                     if (rc) return rc;
                 }
         }
-        rc = time_plan(ctx, pr, leaves, reps, s, &out_sec[i], true);
+        rc = time_plan(ctx, pr, leaves, reps, s, &out_sec[i], true,
+                       ctx->interval_timing ? &ctx->interval_sec[i] : nullptr);
         if (rc) return rc;
         if (ctx->progress_every > 0 && (i + 1) % ctx->progress_every == 0)
             std::fprintf(stderr, "[smoothgemm] sweep %lld / %lld shapes\n", (long long)(i + 1), (long long)n);
@@ -847,6 +932,20 @@ extern "C" int sg_mem_sweep(sg_ctx* ctx, const sg_shape* shapes, int64_t n, int 
     release();
     (void)hipFree(sink);
     return rc;
+}
+
+extern "C" int sg_ctx_set_interval_timing(sg_ctx* ctx, int on) {
+    if (!ctx || (on != 0 && on != 1)) return fail(SG_EINVAL, "bad argument");
+    ctx->interval_timing = on;
+    return SG_OK;
+}
+
+extern "C" int sg_sweep_interval_times(const sg_ctx* ctx, double* out_sec, int64_t n) {
+    if (!ctx || (n > 0 && !out_sec)) return fail(SG_EINVAL, "NULL argument");
+    if ((size_t)n != ctx->interval_sec.size())
+        return fail(SG_EINVAL, "the most recent sweep did not record " + std::to_string(n) + " interval times");
+    std::copy(ctx->interval_sec.begin(), ctx->interval_sec.end(), out_sec);
+    return SG_OK;
 }
 
 extern "C" int sg_sweep_kernel_times(const sg_ctx* ctx, int64_t* launches, double* seconds,

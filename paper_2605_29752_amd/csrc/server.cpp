@@ -83,6 +83,7 @@ struct Req {
     uint64_t ticket = 0, id = 0;
     int64_t M = 0;
     int w = 0;
+    int tile = 0;             // tile shape this request runs with (its class)
     int64_t a_offset = 0;     // element offset of A in the activation pool
     size_t offA = 0, offC = 0, bytesA = 0, bytesC = 0;
     double t_arr = 0, t_adm = 0, t_launch = 0, t_done = 0;
@@ -145,6 +146,7 @@ void fill_completion(const sg_server* sv, const Req& r, sg_completion* c) {
     c->weight = r.w;
     c->status = r.status;
     c->a_offset = r.a_offset;
+    c->tile = r.tile;
     c->t_arrival = r.t_arr;
     c->t_admit = r.t_adm;
     c->t_launch = r.t_launch;
@@ -212,19 +214,35 @@ bool worker_pass(sg_server* sv) {
             progress = true;
         }
     }
-    // 3. launch onto free slots
+    // 3. launch onto free slots: a group is the oldest admitted request and the admitted
+    //    requests after it of the same tile class (every launch runs one tile shape), oldest
+    //    first, at most an equal share of the admitted requests per free slot, so that work
+    //    admitted together spreads over the free slots and runs side by side
+    int free_slots = 0;
+    for (const Slot& sl : sv->slots) free_slots += sl.busy ? 0 : 1;
     for (Slot& sl : sv->slots) {
         if (sl.busy) continue;
         std::vector<Req*> group;
         {
             std::lock_guard<std::mutex> lk(sv->mu);
-            const int cap = sv->cfg.mode == SG_SERVE_GROUPED ? sv->cfg.max_group : 1;
-            while (!sv->admitted.empty() && (int)group.size() < cap) {
-                group.push_back(&sv->reqs[sv->admitted.front()]);
-                sv->admitted.pop_front();
+            const int share = (int)((sv->admitted.size() + free_slots - 1) / std::max(free_slots, 1));
+            const int cap = sv->cfg.mode == SG_SERVE_GROUPED ? std::max(1, std::min(sv->cfg.max_group, share)) : 1;
+            --free_slots;
+            if (!sv->admitted.empty()) {
+                const int cls = sv->reqs[sv->admitted.front()].tile;
+                for (auto it = sv->admitted.begin(); it != sv->admitted.end() && (int)group.size() < cap;) {
+                    Req& r = sv->reqs[*it];
+                    if (r.tile == cls) {
+                        group.push_back(&r);
+                        it = sv->admitted.erase(it);
+                    } else {
+                        ++it;
+                    }
+                }
             }
         }
         if (group.empty()) break;
+        const int tile = group[0]->tile;
         const double t = now_s(sv->t0);
         std::vector<sg_problem> probs(group.size());
         for (size_t i = 0; i < group.size(); ++i) {
@@ -239,27 +257,30 @@ bool worker_pass(sg_server* sv) {
             sl.tickets.push_back(r.ticket);
         }
         int rc = SG_OK;
-        if (sv->cfg.mode == SG_SERVE_GROUPED) {
+        if (probs.size() > 1) {
             int total = 0, grid = 0;
             double fl = 0;
             bool aa = false;
             std::vector<int> order(group.size());
-            rc = grouped_fill(probs.data(), (int)probs.size(), sv->cfg.tile, SG_BF16, true, sl.h_desc,
+            rc = grouped_fill(probs.data(), (int)probs.size(), tile, SG_BF16, true, sl.h_desc,
                               order.data(), &total, &fl, &aa);
-            if (rc == SG_OK) rc = grouped_grid(sv->cfg.tile, aa, sv->device, total, 0, &grid);
+            if (rc == SG_OK) rc = grouped_grid(tile, aa, sv->device, total, 0, &grid);
             if (rc == SG_OK && hipMemcpyAsync(sl.d_desc, sl.h_desc, sizeof(GroupProblem) * probs.size(),
                                               hipMemcpyHostToDevice, sl.s) != hipSuccess)
                 rc = SG_EHIP;
             if (rc == SG_OK)
-                rc = grouped_enqueue(sv->cfg.tile, aa, sl.d_desc, (int)probs.size(), total, grid, SG_BF16,
+                rc = grouped_enqueue(tile, aa, sl.d_desc, (int)probs.size(), total, grid, SG_BF16,
                                      sl.d_counters, sl.s, nullptr, nullptr);
         } else {
+            // a single request (per-request mode, or a group of one) runs the tile kernel
+            // directly: no descriptors to stage, no work queue; the same tile body, so the
+            // result is the one the grouped kernel would give it
             const sg_problem& q = probs[0];
             LaunchDesc d{};
             d.M = q.M; d.N = q.N; d.K = q.K; d.Ml = q.M; d.Nl = q.N; d.Kl = q.K;
             d.A = (const uint16_t*)q.A; d.lda = q.lda; d.B = (const uint16_t*)q.B; d.ldb = q.ldb;
             d.C = q.C; d.ldc = q.ldc; d.out_bf16 = 1; d.add = nullptr; d.ldadd = 0; d.add_kind = ADD_NONE;
-            rc = launch_variant(sv->cfg.tile * kSplitLevels, d, nullptr, sl.s);
+            rc = launch_variant(tile * kSplitLevels, d, nullptr, sl.s);
         }
         if (rc == SG_OK && hipEventRecord(sl.ev, sl.s) != hipSuccess) rc = SG_EHIP;
         if (rc != SG_OK) {
@@ -309,6 +330,7 @@ int sg_server_create(sg_ctx* ctx, const sg_server_cfg* cfg, sg_server** out) {
     if (cfg->hbm_budget < (1u << 20) || cfg->max_inflight < 1 || cfg->max_inflight > 16 ||
         cfg->max_group < 1 || cfg->max_group > 4096 || cfg->queue_cap < 1 || cfg->n_weights < 1 ||
         !cfg->weights || cfg->tile < 0 || cfg->tile >= kNumGroupTiles || cfg->max_m < 1 ||
+        cfg->small_m < 0 || cfg->small_tile < 0 || cfg->small_tile >= kNumGroupTiles ||
         (cfg->mode != SG_SERVE_GROUPED && cfg->mode != SG_SERVE_PER_REQUEST))
         return fail(SG_EINVAL, "bad server configuration");
     int64_t maxK = 0;
@@ -373,6 +395,7 @@ int sg_server_submit(sg_server* sv, const sg_request* req, double arrival_s, uin
     r.id = req->id;
     r.M = req->M;
     r.w = req->weight;
+    r.tile = req->M <= sv->cfg.small_m ? sv->cfg.small_tile : sv->cfg.tile;
     const int64_t span = sv->act_elems - req->M * w.K;
     r.a_offset = (int64_t)(mix64(sv->cfg.seed ^ mix64(req->id + 1)) % (uint64_t)(span / 8 + 1)) * 8;
     r.t_arr = arrival_s >= 0 ? arrival_s : now_s(sv->t0);
@@ -440,19 +463,23 @@ int sg_server_destroy(sg_server* sv) {
     if (!sv) return SG_OK;
     sv->stop.store(true);
     if (sv->worker.joinable()) sv->worker.join();
-    (void)hipDeviceSynchronize();
+    // every resource is released even after a failure; the first HIP error is reported
+    hipError_t first = hipDeviceSynchronize();
+    auto note = [&](hipError_t e) {
+        if (first == hipSuccess) first = e;
+    };
     for (Slot& sl : sv->slots) {
-        if (sl.s) (void)hipStreamDestroy(sl.s);
-        if (sl.ev) (void)hipEventDestroy(sl.ev);
-        if (sl.h_desc) (void)hipHostFree(sl.h_desc);
-        if (sl.d_desc) (void)hipFree(sl.d_desc);
-        if (sl.d_counters) (void)hipFree(sl.d_counters);
+        if (sl.s) note(hipStreamDestroy(sl.s));
+        if (sl.ev) note(hipEventDestroy(sl.ev));
+        if (sl.h_desc) note(hipHostFree(sl.h_desc));
+        if (sl.d_desc) note(hipFree(sl.d_desc));
+        if (sl.d_counters) note(hipFree(sl.d_counters));
     }
-    if (sv->arena) (void)hipFree(sv->arena);
-    if (sv->act_pool) (void)hipFree(sv->act_pool);
+    if (sv->arena) note(hipFree(sv->arena));
+    if (sv->act_pool) note(hipFree(sv->act_pool));
     delete sv->pool;
     delete sv;
-    return SG_OK;
+    return first == hipSuccess ? SG_OK : hip_fail(first, "server teardown");
 }
 
 int sg_serve_poisson(sg_server* sv, double rate, double duration_s, double warmup_s, uint64_t seed,
@@ -534,6 +561,92 @@ int sg_serve_poisson(sg_server* sv, double rate, double duration_s, double warmu
     for (double x : lat) s += x;
     rep->mean_ms = lat.empty() ? NAN : s / lat.size() * 1e3;
     rep->launches = st.launches;
+    rep->peak_bytes = st.peak_bytes;
+    return SG_OK;
+}
+
+int sg_serve_closed(sg_server* sv, int outstanding, double duration_s, double warmup_s, uint64_t seed,
+                    int64_t max_m, sg_serve_report* rep) {
+    if (!sv || !rep || outstanding < 1 || duration_s <= 0 || warmup_s < 0 || warmup_s >= duration_s ||
+        max_m < 1 || max_m > sv->cfg.max_m)
+        return fail(SG_EINVAL, "bad arguments");
+    *rep = sg_serve_report{};
+    sg_server_stats st0{};
+    sg_server_stats_get(sv, &st0);
+    std::mt19937_64 rng(seed);
+    std::uniform_real_distribution<double> u01(0.0, 1.0);
+    std::uniform_int_distribution<int> wsel(0, (int)sv->weights.size() - 1);
+    const double lnmax = std::log((double)max_m);
+    double t_start = 0;
+    sg_server_now(sv, &t_start);
+    const double t_stop = t_start + duration_s;
+    uint64_t id = 0;
+    int in_flight = 0;
+    auto submit_one = [&]() -> int {
+        sg_request r;
+        r.id = id++;
+        r.M = std::min<int64_t>(max_m, std::max<int64_t>(1, std::llround(std::exp(u01(rng) * lnmax))));
+        r.weight = wsel(rng);
+        uint64_t tk = 0;
+        const int rc = sg_server_submit(sv, &r, -1.0, &tk);
+        if (rc == SG_OK) ++in_flight;
+        return rc;
+    };
+    std::vector<sg_completion> comp(1024);
+    std::vector<double> lat;
+    double flops = 0, first = INFINITY, last = 0;
+    int64_t measured = 0, failed = 0;
+    auto collect = [&](bool count) {
+        int n = 0;
+        sg_server_poll(sv, comp.data(), (int)comp.size(), &n);
+        for (int i = 0; i < n; ++i) {
+            const sg_completion& c = comp[i];
+            --in_flight;
+            if (c.status != 0) { ++failed; continue; }
+            if (!count || c.t_arrival - t_start < warmup_s || c.t_arrival >= t_stop) continue;
+            lat.push_back(c.t_done - c.t_arrival);
+            flops += 2.0 * (double)c.M * (double)c.N * (double)c.K;
+            first = std::min(first, c.t_arrival);
+            last = std::max(last, c.t_done);
+            ++measured;
+        }
+        return n;
+    };
+    for (;;) {                       // keep `outstanding` requests in the server until the end
+        double now = 0;
+        sg_server_now(sv, &now);
+        if (now >= t_stop) break;
+        while (in_flight < outstanding) {
+            const int rc = submit_one();
+            if (rc == SG_EAGAIN) break;
+            if (rc) return rc;
+        }
+        if (collect(true) == 0) std::this_thread::sleep_for(std::chrono::microseconds(20));
+    }
+    int rc = sg_server_drain(sv, 600.0);
+    if (rc) return rc;
+    collect(true);
+    std::sort(lat.begin(), lat.end());
+    auto pct = [&](double p) {
+        if (lat.empty()) return (double)NAN;
+        size_t k = (size_t)std::ceil(p * lat.size());   // nearest rank
+        k = std::min(std::max<size_t>(k, 1), lat.size());
+        return lat[k - 1];
+    };
+    sg_server_stats st{};
+    sg_server_stats_get(sv, &st);
+    rep->offered = (int64_t)id;
+    rep->failed = failed;
+    rep->measured = measured;
+    rep->window_s = (measured > 0) ? last - first : 0.0;
+    rep->req_per_s = rep->window_s > 0 ? measured / rep->window_s : 0.0;
+    rep->tflops = rep->window_s > 0 ? flops / rep->window_s / 1e12 : 0.0;
+    rep->p50_ms = pct(0.50) * 1e3;
+    rep->p99_ms = pct(0.99) * 1e3;
+    double sum = 0;
+    for (double x : lat) sum += x;
+    rep->mean_ms = lat.empty() ? NAN : sum / lat.size() * 1e3;
+    rep->launches = st.launches - st0.launches;
     rep->peak_bytes = st.peak_bytes;
     return SG_OK;
 }

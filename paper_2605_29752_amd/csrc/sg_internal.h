@@ -51,7 +51,12 @@ enum { ADD_NONE = 0, ADD_F32 = 1, ADD_BF16 = 2 };
 
 constexpr int kNumTiles = 8;
 constexpr int kSplitLevels = 4;               // S = 1, 2, 4, 8
-constexpr int kNumVariants = kNumTiles * kSplitLevels;
+constexpr int kNumSplitVariants = kNumTiles * kSplitLevels;
+// Stream-K variants follow the split-K ones: variant kSkBase + t runs tile t (0..6) with the K
+// iterations of all its tiles shared evenly by every resident work-group.
+constexpr int kSkBase = kNumSplitVariants;
+constexpr int kNumSkTiles = 7;
+constexpr int kNumVariants = kNumSplitVariants + kNumSkTiles;
 constexpr int kBK = 64;
 // Tile 7 is 64 x 64 with 128-deep K stages (tile 6 with 64-deep ones): per call only, the
 // persistent grouped kernel carries tiles 0 .. kNumGroupTiles - 1.
@@ -62,8 +67,10 @@ constexpr int kDeepBK = 128;
 struct TileShape { int bm, bn; };
 extern const TileShape kTiles[kNumTiles];
 
-inline int variant_tile(int v) { return v / kSplitLevels; }
-inline int variant_splits(int v) { return 1 << (v % kSplitLevels); }
+inline bool variant_is_sk(int v) { return v >= kSkBase; }
+inline int variant_tile(int v) { return variant_is_sk(v) ? v - kSkBase : v / kSplitLevels; }
+// Parallel split-K factor (1 for stream-K variants, which split K across work-groups their own way).
+inline int variant_splits(int v) { return variant_is_sk(v) ? 1 : 1 << (v % kSplitLevels); }
 // K granularity of a split (a K stage never straddles two split ranges).
 inline int tile_split_granule(int tile) { return tile == kDeepTile ? kDeepBK : kBK; }
 
@@ -72,6 +79,9 @@ void split_geometry(int variant, int64_t Kl, int* splits, int64_t* k_chunk);
 // Workspace bytes the variant needs for this launch: split-K partials, plus zero-padded copies
 // of operands the direct-to-LDS kernel cannot read in place (0 when neither applies).
 size_t launch_workspace_bytes(int variant, const LaunchDesc& d);
+// Whether the launch runs a second kernel after the tile kernel (a split-K reduction, or the
+// fix-up of a stream-K launch whose work-group ranges split a tile).
+bool launch_has_second_kernel(int variant, const LaunchDesc& d);
 // Enqueue one launch (operand copies if any, the tile kernel, and for S > 1 its reduction).
 // ws must hold launch_workspace_bytes, or be null: then a split-K launch fails and operands
 // that need a copy are read by the element-wise body instead.
@@ -105,6 +115,9 @@ int grouped_grid(int tile, bool all_aligned, int device, int total_tiles, int gr
 int grouped_enqueue(int tile, bool all_aligned, const GroupProblem* d_probs, int G, int total_tiles,
                     int grid, int c_dtype, int* d_counters, hipStream_t s, hipEvent_t start,
                     hipEvent_t stop);
+
+// The dispatch table a context borrows (NULL if none); defined with the context.
+const struct ::sg_table* ctx_table(const struct ::sg_ctx* ctx);
 
 // Device generator launcher.
 int launch_fill(uint16_t* dst, int64_t n, uint64_t seed, uint64_t stream_id, int64_t offset,

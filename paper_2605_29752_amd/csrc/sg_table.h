@@ -3,7 +3,9 @@
 #pragma once
 
 #include <stdint.h>
+#include <mutex>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "../../include/smoothgemm.h"
@@ -23,6 +25,12 @@ struct sg_table {
     int cus = 0;
     int hip_runtime = 0;
     int c_dtype = -1;               // output type the timings were measured with (-1 unknown)
+    // Grouped-launch schedules found by the grouped autotuner, keyed by a hash of the group's
+    // problem list: later plans of the same group take the schedule by lookup instead of
+    // timing candidates again.  Saved and loaded with the table.
+    struct GroupSched { int tile, grid_wgs, order; double seconds; };
+    mutable std::mutex group_mu;
+    mutable std::unordered_map<uint64_t, GroupSched> group_sched;
 
     int64_t cells() const { return (int64_t)grid.n_m * grid.n_n * grid.n_k; }
     int64_t cell_index(int m, int n, int k) const {

@@ -270,6 +270,13 @@ int sg_table_plan_leaves(const sg_table* t, int64_t M, int64_t N, int64_t K, int
     return SG_OK;
 }
 
+int sg_table_group_count(const sg_table* t, int64_t* n) {
+    if (!t || !n) return fail(SG_EINVAL, "NULL argument");
+    std::lock_guard<std::mutex> lk(t->group_mu);
+    *n = (int64_t)t->group_sched.size();
+    return SG_OK;
+}
+
 static const char kMagic[8] = {'S', 'G', 'T', 'B', 'L', '0', '0', '1'};
 
 int sg_table_save(const sg_table* t, const char* path) {
@@ -289,6 +296,17 @@ int sg_table_save(const sg_table* t, const char* path) {
     w(&t->nvar, 4);
     w(t->variants.data(), sizeof(int) * t->nvar);
     w(t->T0.data(), sizeof(double) * t->T0.size());
+    {   // grouped-launch schedules (a trailing section; files without it load with none)
+        std::lock_guard<std::mutex> lk(t->group_mu);
+        const uint32_t ns = (uint32_t)t->group_sched.size();
+        w(&ns, 4);
+        for (const auto& kv : t->group_sched) {
+            const int32_t v[3] = {kv.second.tile, kv.second.grid_wgs, kv.second.order};
+            w(&kv.first, 8);
+            w(v, sizeof v);
+            w(&kv.second.seconds, 8);
+        }
+    }
     ok = (std::fclose(f) == 0) && ok;
     return ok ? SG_OK : fail(SG_EIO, std::string("write failed: ") + path);
 }
@@ -326,6 +344,22 @@ int sg_table_load(const char* path, int force, sg_table** out) {
         r(t->variants.data(), sizeof(int) * t->nvar);
         t->T0.resize((size_t)t->nvar * t->cells());
         r(t->T0.data(), sizeof(double) * t->T0.size());
+    }
+    if (ok) {
+        uint32_t ns = 0;
+        if (std::fread(&ns, 1, 4, f) == 4) {           // optional trailing section
+            ok = ns <= (1u << 24);
+            for (uint32_t i = 0; i < ns && ok; ++i) {
+                uint64_t key = 0;
+                int32_t v[3] = {0, 0, 0};
+                double sec = 0.0;
+                r(&key, 8);
+                r(v, sizeof v);
+                r(&sec, 8);
+                ok = ok && v[0] >= 0 && v[0] < kNumGroupTiles && v[1] >= 0 && (v[2] == 0 || v[2] == 1);
+                if (ok) t->group_sched[key] = sg_table::GroupSched{v[0], v[1], v[2], sec};
+            }
+        }
     }
     std::fclose(f);
     if (!ok) {

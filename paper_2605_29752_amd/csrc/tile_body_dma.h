@@ -116,13 +116,15 @@ __device__ __forceinline__ void dma16(const i32x4_t rsrc, uint32_t voffset, uint
         : "memory");
 }
 
+// One tile over the K range [kb, ke) (kb a multiple of the stage depth); kz only selects the
+// split-K output slice (kz * ws_slice).
 // MEM = true gives the memory-only twin of the tile (the paper's memory surface, Sec. 4): the
 // same operand loads into the same ring, the same waits and barriers, and the same stores of C,
 // with the fragment reads and the matrix-core products left out (C is written as zeros, plus
 // the addend if one is fused).
 template <int BM, int BN, bool MEM = false, bool DEEP = false>
-__device__ __forceinline__ void tile_body_dma(const KArgs& p, const int m0, const int n0, const int kz,
-                                              uint16_t* __restrict__ smem) {
+__device__ __forceinline__ void tile_body_dma_range(const KArgs& p, const int m0, const int n0, const int kz,
+                                                    const int kb, const int ke, uint16_t* __restrict__ smem) {
     using T = DmaTile<BM, BN, DEEP>;
     constexpr int WM = BM / 2, WN = BN / 2;
     constexpr int FM = WM / 16, FN = WN / 16;
@@ -133,8 +135,6 @@ __device__ __forceinline__ void tile_body_dma(const KArgs& p, const int m0, cons
     const int wm = wave >> 1, wn = wave & 1;
     const int lr = lane & 15, lg = lane >> 4;
 
-    const int kb = kz * p.k_chunk;
-    const int ke = min(p.Kl, kb + p.k_chunk);
     const int nk = (ke - kb + T::BKD - 1) / T::BKD;
 
     constexpr uint32_t kOut = 0x80000000u;
@@ -327,6 +327,14 @@ __device__ __forceinline__ void tile_body_dma(const KArgs& p, const int m0, cons
         if (epilogue_direct<BM, BN>(p, m0, n0, kz, acc)) return;
     __syncthreads();                            // ring no longer read: the epilogue reuses it
     epilogue<BM, BN>(p, m0, n0, kz, smem, acc);
+}
+
+// One tile over the K range of split kz: [kz k_chunk, min(Kl, (kz + 1) k_chunk)).
+template <int BM, int BN, bool MEM = false, bool DEEP = false>
+__device__ __forceinline__ void tile_body_dma(const KArgs& p, const int m0, const int n0, const int kz,
+                                              uint16_t* __restrict__ smem) {
+    const int kb = kz * p.k_chunk;
+    tile_body_dma_range<BM, BN, MEM, DEEP>(p, m0, n0, kz, kb, min(p.Kl, kb + p.k_chunk), smem);
 }
 
 }  // namespace sg

@@ -52,3 +52,26 @@ def test_noise_has_no_strong_period():
     rng = np.random.default_rng(0)
     st = bench.sawtooth(500.0 + rng.normal(0, 5, Ns.size), Ns, 128)
     assert st["period_autocorr"] < 0.5
+
+
+def test_ramp_texture_split():
+    rng = np.random.default_rng(3)
+    n = 8
+    # a landscape monotone along every axis has no texture: its roughness is all ramp
+    g = np.meshgrid(*[np.arange(n)] * 3, indexing="ij")
+    mono = 10.0 * g[0] + 3.0 * g[1] ** 2 + np.sqrt(g[2] + 1.0)
+    rt = bench.ramp_texture(mono)
+    assert rt["texture_3d"] == pytest.approx(0.0, abs=1e-12)
+    # ramp + texture is the roughness, line by line, on any landscape
+    x = rng.uniform(0, 100, size=(n, n, n))
+    rt = bench.ramp_texture(x)
+    for name, axis in (("m", 0), ("n", 1), ("k", 2)):
+        t = np.moveaxis(x, axis, -1)
+        rough = float(np.mean(np.abs(np.diff(t, axis=-1)).sum(axis=-1) / (n - 1)))
+        assert rt["ramp_" + name] + rt["texture_" + name] == pytest.approx(rough)
+        assert rt["texture_" + name] >= 0
+    # a zig-zag with equal end points is all texture
+    z = np.zeros((1, 1, 9))
+    z[..., 1::2] = 5.0
+    rt = bench.ramp_texture(np.broadcast_to(z, (2, 2, 9)).copy())
+    assert rt["ramp_k"] == 0.0 and rt["texture_k"] == pytest.approx(5.0)

@@ -39,15 +39,21 @@ def test_library_exports_every_declared_symbol():
 
 def test_variant_family():
     n = sg.num_variants()
-    assert n == 32
+    assert n == 39                      # 8 tiles x 4 split-K levels, then stream-K on tiles 0..6
     seen = set()
     for v in range(n):
         info = sg.variant_info(v)
         assert info.lds_bytes <= 160 * 1024
-        assert info.bk == (128 if v // 4 == 7 else 64) and info.splits == 1 << (v % 4)
+        if v < 32:
+            assert info.bk == (128 if v // 4 == 7 else 64) and info.splits == 1 << (v % 4)
+        else:
+            assert info.bk == 64 and info.splits == 0 and info.name.endswith("_sk")
+            plain = sg.variant_info(4 * (v - 32))
+            assert (info.bm, info.bn) == (plain.bm, plain.bn)
         seen.add((info.bm, info.bn, info.bk, info.splits))
     assert len(seen) == n
     assert sg.variant_info(28).name == "64x64x128_s1"
+    assert sg.variant_info(35).name == "128x128x64_sk"
     with pytest.raises(sg.SGError):
         sg.variant_info(n)
 
@@ -149,6 +155,16 @@ def test_first_principles_landscapes_match_oracle():
                 assert ideal[a, b, c] == pytest.approx(om.ideal_tflops(M, N, 2516.6, 256, 256), rel=1e-12)
                 assert opt[a, b, c] == pytest.approx(
                     om.optimal_tflops(M, N, K, 2516.6, 256, 8000.0, tiles=(256, 128, 64), c_bytes=2), rel=1e-12)
+    # the memory-channel term: the library against the oracle with the paper's Arc B580 constants
+    b580hw = {"peak_tflops": 108.2, "cores": 20, "bw_gbs": 451.0}
+    och = sg.optimal_landscape(step, nm, nn, nk, tiles=(256, 128, 64), c_bytes=4, hw=b580hw, channels=6)
+    for a in range(nm):
+        for b in range(nn):
+            for c in range(nk):
+                M, N, K = (a + 1) * step, (b + 1) * step, (c + 1) * step
+                assert och[a, b, c] == pytest.approx(
+                    om.optimal_tflops(M, N, K, 108.2, 20, 451.0, tiles=(256, 128, 64), c_bytes=4, channels=6),
+                    rel=1e-12)
     # the paper's own ideal through the library: Arc B580 constants (Sec. 9.1)
     b580 = sg.ideal_landscape(128, 32, 32, 2, tile=256, hw={"peak_tflops": 108.2, "cores": 20, "bw_gbs": 451.0})
     st = sg.landscape_stats(b580)

@@ -9,7 +9,7 @@ from gpu_helpers import TOL, check_exact, check_tol, inputs, run_gemm, say
 pytestmark = pytest.mark.gpu
 
 sg = pytest.importorskip("paper_2605_29752_amd")
-NV = 32
+NV = 39          # every variant: 8 tiles x 4 split-K levels, then stream-K on tiles 0..6
 F32, BF16 = 0, 1
 
 

@@ -11,7 +11,7 @@ from gpu_helpers import inputs, say
 pytestmark = pytest.mark.gpu
 
 sg = pytest.importorskip("paper_2605_29752_amd")
-NV = 32
+NV = 32          # variants with a memory-only twin (stream-K variants have none)
 F32, BF16 = 0, 1
 
 

@@ -47,18 +47,19 @@ def _serve_and_check(ctx, weights, mode, budget, n_req=60, max_group=8):
         for c in srv.poll(256):
             A = device_bytes(c.A, c.M * c.K * 2).view(np.uint16).reshape(c.M, c.K)
             Cb = device_bytes(c.C, c.M * c.N * 2).view(np.uint16).reshape(c.M, c.N)
-            comps.append((c.M, c.N, c.K, c.weight, c.status, c.a_offset, A, Cb))
+            comps.append((c.M, c.N, c.K, c.weight, c.status, c.a_offset, A, Cb, c.tile))
             srv.release(c.ticket)
     assert len(comps) == n_req and all(c[4] == 0 for c in comps)
     st = srv.stats()
     assert st["peak_bytes"] <= budget and st["completed"] == n_req
     say("mode", mode, "launches", st["launches"], "peak bytes", st["peak_bytes"])
-    for (M, N, K, w, status, a_offset, A, Cb) in comps:
+    for (M, N, K, w, status, a_offset, A, Cb, tile) in comps:
+        assert tile == (6 if M <= 64 else 3)
         want_a = synth.f32_to_bf16_bits(synth.normal_f32(ASEED, 0, M * K, 0.02, start=a_offset)).reshape(M, K)
         assert np.array_equal(A, want_a), "staged activation differs from the seeded pool"
         # alone: the same tile shape through the per-call entry point
         alone = torch.empty(M, N, dtype=torch.bfloat16, device="cuda")
-        ctx.gemm(sg.to_device_bf16(A), ws[w].view(K, N), alone, mode=sg.MODE_VARIANT, variant=12)
+        ctx.gemm(sg.to_device_bf16(A), ws[w].view(K, N), alone, mode=sg.MODE_VARIANT, variant=4 * tile)
         torch.cuda.synchronize()
         assert np.array_equal(sg.bf16_tensor_bits(alone), Cb), "served result differs from alone"
         check_tol(synth.bf16_bits_to_f32(Cb).astype(np.float64), A, host[w], BF16)
@@ -106,3 +107,17 @@ def test_poisson_smoke(ctx, weights):
     assert rep["failed"] == 0 and rep["measured"] > 100
     assert 0 < rep["p50_ms"] <= rep["p99_ms"]
     srv.close()
+
+
+def test_closed_loop_saturation_smoke(ctx, weights):
+    shapes, ws, host = weights
+    for mode in (sg.SERVE_GROUPED, sg.SERVE_PER_REQUEST):
+        srv = sg.Server(ctx, [(K, N, t.data_ptr(), N) for (K, N), t in zip(shapes, ws)],
+                        hbm_budget=256 << 20, max_m=600, seed=ASEED, mode=mode)
+        rep = srv.serve_closed(32, 1.0, 0.2, 3, max_m=600)
+        say(mode, rep)
+        assert rep["failed"] == 0 and rep["measured"] > 50 and rep["req_per_s"] > 0
+        assert 0 < rep["p50_ms"] <= rep["p99_ms"]
+        if mode == sg.SERVE_GROUPED:
+            assert rep["launches"] < rep["offered"]      # 32 outstanding requests share launches
+        srv.close()

@@ -111,3 +111,19 @@ def test_deep_k_kernel_codegen(asm):
     assert len(entry) == 1
     for key in (".vgpr_spill_count", ".sgpr_spill_count"):
         assert re.findall(re.escape(key) + r":\s+(\d+)", entry[0]) == ["0"], key
+
+
+@pytest.mark.parametrize("bm,bn", TILES)
+def test_stream_k_kernel_codegen(asm, bm, bn):
+    """The stream-K kernels run the same tile body once per segment of their range: MFMAs, no
+    accumulator copies, no spills."""
+    name = "_ZN2sg19sg_gemm_tile_dma_skILi%dELi%dEEEvNS_5KArgsENS_6SkArgsE" % (bm, bn)
+    body = kernel_body(asm, name)
+    assert re.search(r"v_mfma_f32_16x16x32_bf16", body)
+    bad = _accumulator_copies(body)
+    assert not bad, "accumulators copied between MFMAs: %s" % bad[:4]
+    meta = asm[asm.index("amdhsa.kernels:"):]
+    entry = [e for e in meta.split("\n  - ") if re.search(r"\.name:\s+" + name + r"\s", e)]
+    assert len(entry) == 1
+    for key in (".vgpr_spill_count", ".sgpr_spill_count"):
+        assert re.findall(re.escape(key) + r":\s+(\d+)", entry[0]) == ["0"], key
