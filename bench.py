@@ -659,18 +659,41 @@ def run_concurrent(args, sg, torch, ctx, stream):
     ksum = np.empty(len(split))     # sequential, sum of kernel times (the table's cost model)
     seq = np.empty(len(split))      # sequential, between stream markers
     conc = np.empty(len(split))     # concurrent pieces, between stream markers
+    grp = np.empty(len(split))      # pieces as one grouped launch (same-tile plans), markers
     ksum[order] = ctx.sweep(shapes, A, B, C, mode=sg.MODE_DP, c_dtype=sg.BF16, warmup=args.shape_warmup,
                             reps=args.reps, stream=stream)
     try:
-        for mode, out in ((2, seq), (1, conc)):
+        for mode, out in ((2, seq), (1, conc), (3, grp)):
             ctx.set_concurrent_splits(mode)
             out[order] = ctx.sweep(shapes, A, B, C, mode=sg.MODE_DP, c_dtype=sg.BF16,
                                    warmup=args.shape_warmup, reps=args.reps, stream=stream)
     finally:
         ctx.set_concurrent_splits(0)
     fl = np.array([2.0 * m * nn * k for m, nn, k in split])
-    tf_seq, tf_conc = fl / seq / 1e12, fl / conc / 1e12
+    tf_seq, tf_conc, tf_grp = fl / seq / 1e12, fl / conc / 1e12, fl / grp / 1e12
     r = seq / conc
+    # which split cells the grouped form can take: every piece on one tile shape, no split-K
+    def groupable(c):
+        recs = []
+        stack = [c]
+        vs = set()
+        while stack:
+            m, nn, k = stack.pop()
+            rec = table.lookup(m, nn, k)
+            if rec["action"] in (sg.ACT_AS_IS, sg.ACT_PAD):
+                vs.add(rec["variant"])
+            elif rec["action"] == sg.ACT_SPLIT_M:
+                p = rec["arg"] * step
+                stack += [(p, nn, k), (m - p, nn, k)]
+            elif rec["action"] == sg.ACT_SPLIT_N:
+                p = rec["arg"] * step
+                stack += [(m, p, k), (m, nn - p, k)]
+            else:
+                return False
+        vi = [sg.variant_info(v) for v in vs]
+        return len({(x.bm, x.bn, x.bk) for x in vi}) == 1 and all(x.splits == 1 for x in vi) and vi[0].bk == 64
+    g_ok = np.array([groupable(c) for c in split])
+    rg = seq / grp
     leaves = np.array([table.plan_leaves(*c) for c in split])
     res = {"table_grid": "{%d..%d}^3 step %d" % (step, step * n, step), "table_build_s": table_s,
            "split_cells": len(split), "frac_of_grid": len(split) / len(cells),
@@ -682,9 +705,18 @@ def run_concurrent(args, sg, torch, ctx, stream):
            "frac_slower_10pct": float((r < 1 / 1.1).mean()),
            # marker-timed: the landscape mean would gain this much if each split cell ran the
            # faster of the two executions
-           "landscape_mean_gain_tflops": float(np.sum(np.maximum(tf_conc, tf_seq) - tf_seq) / len(cells))}
-    log("concurrent splits: %d cells, sequential %.1f -> concurrent %.1f TFLOP/s mean, speed-up median %.3f"
-        % (len(split), res["sequential_mean_tflops"], res["concurrent_mean_tflops"], res["speedup_median"]))
+           "landscape_mean_gain_tflops": float(np.sum(np.maximum(tf_conc, tf_seq) - tf_seq) / len(cells)),
+           # the same pieces as one persistent grouped launch, where every piece runs one tile shape
+           "grouped_cells": int(g_ok.sum()),
+           "grouped_mean_tflops": float(tf_grp[g_ok].mean()) if g_ok.any() else None,
+           "grouped_sequential_mean_tflops": float(tf_seq[g_ok].mean()) if g_ok.any() else None,
+           "grouped_speedup_median": float(np.median(rg[g_ok])) if g_ok.any() else None,
+           "grouped_frac_faster": float((rg[g_ok] > 1.0).mean()) if g_ok.any() else None,
+           "grouped_landscape_mean_gain_tflops": float(np.sum(np.maximum(tf_grp, tf_seq)[g_ok] - tf_seq[g_ok]) / len(cells))}
+    log("concurrent splits: %d cells, sequential %.1f -> concurrent %.1f TFLOP/s mean, speed-up median %.3f; "
+        "grouped form on %d cells: median speed-up %s"
+        % (len(split), res["sequential_mean_tflops"], res["concurrent_mean_tflops"], res["speedup_median"],
+           res["grouped_cells"], res["grouped_speedup_median"]))
     return res
 
 

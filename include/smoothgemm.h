@@ -76,7 +76,11 @@ int sg_ctx_set_progress(sg_ctx* ctx, int every);
  * on the caller's stream (the fork and a marker after the joins, so fork / join latency is
  * included) and leaves it out of the per-variant kernel accounting.  Plans with K pieces stay
  * sequential.  on = 2 runs such plans one after another on the caller's stream but times them
- * between the same two markers (the like-for-like reference for on = 1).
+ * between the same two markers (the like-for-like reference for on = 1).  on = 3 runs the
+ * pieces of such a plan as ONE persistent grouped launch (the grouped kernel below, its
+ * descriptors copied to a buffer the context keeps) when every piece runs the same tile shape
+ * without split-K or stream-K and beta = 0, else one after another; timed between the same
+ * markers.
  * Default 0: pieces run one after another on the caller's stream, as the paper executes them,
  * and a run's time is the sum of its kernels' times. */
 int sg_ctx_set_concurrent_splits(sg_ctx* ctx, int on);

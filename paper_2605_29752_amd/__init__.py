@@ -352,8 +352,13 @@ class Table:
             check(_lib.sg_table_free(h))
 
     def __del__(self):
-        if _live():
-            self.close()
+        # at interpreter shutdown the module's globals may already be gone: then the process
+        # exit releases the object
+        try:
+            if _live():
+                self.close()
+        except (TypeError, NameError, AttributeError):
+            pass
 
     @staticmethod
     def from_t0(step: int, n_m: int, n_n: int, n_k: int, T0: np.ndarray, variants) -> "Table":
@@ -432,8 +437,13 @@ class Context:
             check(lib().sg_ctx_destroy(h))
 
     def __del__(self):
-        if _live():
-            self.close()
+        # at interpreter shutdown the module's globals may already be gone: then the process
+        # exit releases the object
+        try:
+            if _live():
+                self.close()
+        except (TypeError, NameError, AttributeError):
+            pass
 
     def set_plain_variant(self, v: int):
         check(lib().sg_ctx_set_plain_variant(self.handle, v))
@@ -567,8 +577,13 @@ class GroupPlan:
             check(_lib.sg_group_plan_destroy(h))
 
     def __del__(self):
-        if _live():
-            self.close()
+        # at interpreter shutdown the module's globals may already be gone: then the process
+        # exit releases the object
+        try:
+            if _live():
+                self.close()
+        except (TypeError, NameError, AttributeError):
+            pass
 
 
 class Graph:
@@ -590,8 +605,13 @@ class Graph:
             check(_lib.sg_graph_destroy(h))
 
     def __del__(self):
-        if _live():
-            self.close()
+        # at interpreter shutdown the module's globals may already be gone: then the process
+        # exit releases the object
+        try:
+            if _live():
+                self.close()
+        except (TypeError, NameError, AttributeError):
+            pass
 
 
 class Server:
@@ -660,8 +680,13 @@ class Server:
             check(_lib.sg_server_destroy(h))
 
     def __del__(self):
-        if _live():
-            self.close()
+        # at interpreter shutdown the module's globals may already be gone: then the process
+        # exit releases the object
+        try:
+            if _live():
+                self.close()
+        except (TypeError, NameError, AttributeError):
+            pass
 
 
 def gemm_batch(ctx: "Context", probs, c_dtype: int = BF16, mode: int = MODE_PLAIN, variant: int = 0,

@@ -39,24 +39,26 @@ const TileShape kTiles[kNumTiles] = {{256, 256}, {256, 128}, {128, 256}, {128, 1
 
 // Aligned fast path with direct-to-LDS operand loads (see tile_body_dma.h).
 template <int BM, int BN>
-__global__ __launch_bounds__(256) void sg_gemm_tile_dma(KArgs p) {
-    __shared__ __attribute__((aligned(1024))) uint16_t smem[dma_smem_bytes<BM, BN>() / 2];
+__global__ __launch_bounds__((64 * call_waves<BM, BN>())) void sg_gemm_tile_dma(KArgs p) {
+    constexpr int NW = call_waves<BM, BN>();
+    __shared__ __attribute__((aligned(1024))) uint16_t smem[dma_smem_bytes<BM, BN, false, NW>() / 2];
     int tm, tn;
     tile_coords(p.tiles_m, p.tiles_n, tm, tn);
     const int m0 = tm * BM, n0 = tn * BN;
     if (m0 >= p.M || n0 >= p.N) return;            // padding-only tile
-    tile_body_dma<BM, BN>(p, m0, n0, blockIdx.z, smem);
+    tile_body_dma<BM, BN, false, false, NW>(p, m0, n0, blockIdx.z, smem);
 }
 
 // Memory-only twin of sg_gemm_tile_dma: the same loads, waits and stores, no MFMA work.
 template <int BM, int BN>
-__global__ __launch_bounds__(256) void sg_gemm_tile_dma_mem(KArgs p) {
-    __shared__ __attribute__((aligned(1024))) uint16_t smem[dma_smem_bytes<BM, BN>() / 2];
+__global__ __launch_bounds__((64 * call_waves<BM, BN>())) void sg_gemm_tile_dma_mem(KArgs p) {
+    constexpr int NW = call_waves<BM, BN>();
+    __shared__ __attribute__((aligned(1024))) uint16_t smem[dma_smem_bytes<BM, BN, false, NW>() / 2];
     int tm, tn;
     tile_coords(p.tiles_m, p.tiles_n, tm, tn);
     const int m0 = tm * BM, n0 = tn * BN;
     if (m0 >= p.M || n0 >= p.N) return;
-    tile_body_dma<BM, BN, true>(p, m0, n0, blockIdx.z, smem);
+    tile_body_dma<BM, BN, true, false, NW>(p, m0, n0, blockIdx.z, smem);
 }
 
 // The 64 x 64 tile with 128-deep K stages (tile 7), and its memory-only twin.
@@ -123,9 +125,10 @@ __device__ __forceinline__ int sk_logical(int b, int G) {
 }
 
 template <int BM, int BN>
-__global__ __launch_bounds__(256) void sg_gemm_tile_dma_sk(KArgs p, SkArgs s) {
-    __shared__ __attribute__((aligned(1024))) uint16_t smem[dma_smem_bytes<BM, BN>() / 2];
-    constexpr int BKD = DmaTile<BM, BN>::BKD;
+__global__ __launch_bounds__((64 * call_waves<BM, BN>())) void sg_gemm_tile_dma_sk(KArgs p, SkArgs s) {
+    constexpr int NW = call_waves<BM, BN>();
+    __shared__ __attribute__((aligned(1024))) uint16_t smem[dma_smem_bytes<BM, BN, false, NW>() / 2];
+    constexpr int BKD = DmaTile<BM, BN, false, NW>::BKD;
     const int G = gridDim.x;
     const int g = sk_logical(blockIdx.x, G);
     const int64_t total = (int64_t)s.tiles * s.ipt;
@@ -146,7 +149,7 @@ __global__ __launch_bounds__(256) void sg_gemm_tile_dma_sk(KArgs p, SkArgs s) {
             q.ldc = BN; q.out_bf16 = 0;
             q.add = nullptr; q.add_kind = ADD_NONE; q.vec_ok = 1;
         }
-        tile_body_dma_range<BM, BN>(q, m0, n0, 0, k0 * BKD, min(p.Kl, k1 * BKD), smem);
+        tile_body_dma_range<BM, BN, false, false, NW>(q, m0, n0, 0, k0 * BKD, min(p.Kl, k1 * BKD), smem);
         it += k1 - k0;
     }
 }
@@ -262,7 +265,7 @@ __global__ __launch_bounds__(256) void sg_splitk_reduce4(const float* ws, int64_
 // LDS of the aligned (direct-to-LDS) kernel of a tile: its ring of K stages.
 int lds_bytes_of_tile(int tile) {
     switch (tile) {
-        case 0: return dma_smem_bytes<256, 256>();
+        case 0: return dma_smem_bytes<256, 256, false, call_waves<256, 256>()>();
         case 1: return dma_smem_bytes<256, 128>();
         case 2: return dma_smem_bytes<128, 256>();
         case 3: return dma_smem_bytes<128, 128>();
@@ -338,7 +341,8 @@ static int sk_occupancy() {
     static int occ = -1;
     if (occ < 0) {
         int o = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, sg_gemm_tile_dma_sk<BM, BN>, 256, 0) != hipSuccess || o < 1) {
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, sg_gemm_tile_dma_sk<BM, BN>, 64 * call_waves<BM, BN>(), 0) !=
+                hipSuccess || o < 1) {
             (void)hipGetLastError();
             o = 1;
         }
@@ -449,15 +453,19 @@ static int launch_pack(const uint16_t* src, int64_t lds, int64_t rows, int64_t c
 // occupancy query fails.
 template <int BM, int BN, bool DEEP>
 static int twin_extra_lds() {
+    constexpr int threads = DEEP ? 256 : 64 * call_waves<BM, BN>();
     int occ_gemm = 0, occ_twin = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ_gemm, dma_kernel<BM, BN, DEEP>(false), 256, 0) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ_twin, dma_kernel<BM, BN, DEEP>(true), 256, 0) != hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ_gemm, dma_kernel<BM, BN, DEEP>(false), threads, 0) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ_twin, dma_kernel<BM, BN, DEEP>(true), threads, 0) != hipSuccess ||
         occ_gemm < 1)
         return -1;
     if (occ_twin <= occ_gemm) return 0;
-    const int budget = 160 * 1024 - dma_smem_bytes<BM, BN>();
+    int smem = 0;
+    if constexpr (DEEP) smem = dma_smem_bytes<BM, BN, true>();
+    else smem = dma_smem_bytes<BM, BN, false, call_waves<BM, BN>()>();
+    const int budget = 160 * 1024 - smem;
     for (int extra = 1024; extra <= budget; extra += 1024) {
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ_twin, dma_kernel<BM, BN, DEEP>(true), 256,
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ_twin, dma_kernel<BM, BN, DEEP>(true), threads,
                                                          (size_t)extra) != hipSuccess)
             return -1;
         if (occ_twin <= occ_gemm) return extra;
@@ -531,7 +539,7 @@ static int launch_sk(const LaunchDesc& d, int variant, void* ws, hipStream_t str
     a.vec_ok = vec_c ? 1 : 0;
     if (gm.tiles <= 0) return SG_OK;
     const SkArgs sk{(float*)ws, gm.tiles, gm.ipt};
-    hipExtLaunchKernelGGL(sg_gemm_tile_dma_sk<BM, BN>, dim3((unsigned)gm.G), dim3(256), 0, stream, start,
+    hipExtLaunchKernelGGL(sg_gemm_tile_dma_sk<BM, BN>, dim3((unsigned)gm.G), dim3(64 * call_waves<BM, BN>()), 0, stream, start,
                           gm.fixup ? d.ev_mid : d.ev_stop, 0, a, sk);
     SG_HIP(hipGetLastError());
     if (gm.fixup) {
@@ -601,7 +609,9 @@ static int launch_tile(const LaunchDesc& d, int variant, void* ws, hipStream_t s
     const int64_t nwg = (int64_t)a.tiles_m * a.tiles_n;
     if (nwg <= 0) return SG_OK;
     if (nwg > 0x7FFFFFFF) return fail(SG_EINVAL, "launch grid too large");
-    dim3 grid((unsigned)nwg, 1, (unsigned)S), block(256);
+    // the direct-to-LDS kernels and their twins run call_waves() waves (the deep-K tile four);
+    // the element-wise body always four
+    dim3 grid((unsigned)nwg, 1, (unsigned)S), block(256), block_dma(DEEP ? 256 : 64 * call_waves<BM, BN>());
     hipEvent_t stop1 = (S > 1) ? d.ev_mid : d.ev_stop;
     if (d.mem_only && !aligned)
         return fail(SG_EINVAL, "memory-only twin: operands the direct-to-LDS path cannot load "
@@ -609,10 +619,10 @@ static int launch_tile(const LaunchDesc& d, int variant, void* ws, hipStream_t s
     if (d.mem_only) {
         static const int extra = twin_extra_lds<BM, BN, DEEP>();
         if (extra < 0) { (void)hipGetLastError(); return fail(SG_EHIP, "occupancy query for the memory-only twin failed"); }
-        hipExtLaunchKernelGGL(dma_kernel<BM, BN, DEEP>(true), grid, block, (size_t)extra, stream, start, stop1, 0, a);
+        hipExtLaunchKernelGGL(dma_kernel<BM, BN, DEEP>(true), grid, block_dma, (size_t)extra, stream, start, stop1, 0, a);
     }
     else if (aligned)
-        hipExtLaunchKernelGGL(dma_kernel<BM, BN, DEEP>(false), grid, block, 0, stream, start, stop1, 0, a);
+        hipExtLaunchKernelGGL(dma_kernel<BM, BN, DEEP>(false), grid, block_dma, 0, stream, start, stop1, 0, a);
     else
         hipExtLaunchKernelGGL((sg_gemm_tile<BM, BN>), grid, block, 0, stream, start, stop1, 0, a);
     SG_HIP(hipGetLastError());

@@ -23,13 +23,18 @@ namespace sg {
 
 // ALL_ALIGNED: every problem of the launch takes the aligned fast path, so the kernel does not
 // carry the element-wise fallback body (fewer registers, more resident work-groups).
+// Waves of a grouped kernel: the per-call kernels' count when every problem is aligned (so the
+// tile body is the same), four when the element-wise body (written for four waves) may run.
 template <int BM, int BN, bool ALL_ALIGNED>
-__global__ __launch_bounds__(256) void sg_gemm_grouped(const GroupProblem* __restrict__ probs, int G,
-                                                        int total_tiles, int out_bf16,
-                                                        int* __restrict__ counters) {
+constexpr int grouped_waves() { return ALL_ALIGNED ? call_waves<BM, BN>() : 4; }
+
+template <int BM, int BN, bool ALL_ALIGNED>
+__global__ __launch_bounds__((64 * grouped_waves<BM, BN, ALL_ALIGNED>())) void sg_gemm_grouped(
+        const GroupProblem* __restrict__ probs, int G, int total_tiles, int out_bf16, int* __restrict__ counters) {
+    constexpr int NW = grouped_waves<BM, BN, ALL_ALIGNED>();
     // the aligned body's ring, or the larger of it and the element-wise body's stages
-    constexpr int kSmem = (ALL_ALIGNED || dma_smem_bytes<BM, BN>() / 2 > smem_elems<BM, BN>())
-                              ? dma_smem_bytes<BM, BN>() / 2 : smem_elems<BM, BN>();
+    constexpr int kSmem = (ALL_ALIGNED || dma_smem_bytes<BM, BN, false, NW>() / 2 > smem_elems<BM, BN>())
+                              ? dma_smem_bytes<BM, BN, false, NW>() / 2 : smem_elems<BM, BN>();
     __shared__ __attribute__((aligned(1024))) uint16_t smem[kSmem];
     __shared__ int s_tile;
     for (;;) {
@@ -57,7 +62,7 @@ __global__ __launch_bounds__(256) void sg_gemm_grouped(const GroupProblem* __res
         a.vec_ok = q.vec_ok;
         a.a_bytes = q.a_bytes; a.b_bytes = q.b_bytes;
         if (ALL_ALIGNED || q.aligned) {
-            tile_body_dma<BM, BN>(a, tm * BM, tn * BN, 0, smem);
+            tile_body_dma<BM, BN, false, false, NW>(a, tm * BM, tn * BN, 0, smem);
         } else {
             if constexpr (!ALL_ALIGNED) tile_body<BM, BN>(a, tm * BM, tn * BN, 0, smem);
         }
@@ -89,6 +94,19 @@ static GroupedKernel grouped_kernel_t(int tile) {
 
 static GroupedKernel grouped_kernel(int tile, bool all_aligned) {
     return all_aligned ? grouped_kernel_t<true>(tile) : grouped_kernel_t<false>(tile);
+}
+
+static int grouped_threads(int tile, bool all_aligned) {
+    if (!all_aligned) return 256;
+    switch (tile) {
+        case 0: return 64 * call_waves<256, 256>();
+        case 1: return 64 * call_waves<256, 128>();
+        case 2: return 64 * call_waves<128, 256>();
+        case 3: return 64 * call_waves<128, 128>();
+        case 4: return 64 * call_waves<128, 64>();
+        case 5: return 64 * call_waves<64, 128>();
+        default: return 64 * call_waves<64, 64>();
+    }
 }
 
 int grouped_fill(const sg_problem* probs, int G, int tile, int c_dtype, bool lpt, GroupProblem* out,
@@ -130,7 +148,8 @@ int grouped_fill(const sg_problem* probs, int G, int tile, int c_dtype, bool lpt
 
 int grouped_grid(int tile, bool all_aligned, int device, int total_tiles, int grid_wgs, int* grid) {
     int per_cu = 1, cus = 0;
-    SG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, grouped_kernel(tile, all_aligned), 256, 0));
+    SG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, grouped_kernel(tile, all_aligned),
+                                                        grouped_threads(tile, all_aligned), 0));
     SG_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device));
     int g = std::max(1, per_cu) * cus;
     if (grid_wgs > 0) g = grid_wgs;
@@ -141,7 +160,8 @@ int grouped_grid(int tile, bool all_aligned, int device, int total_tiles, int gr
 int grouped_enqueue(int tile, bool all_aligned, const GroupProblem* d_probs, int G, int total_tiles,
                     int grid, int c_dtype, int* d_counters, hipStream_t s, hipEvent_t start,
                     hipEvent_t stop) {
-    hipExtLaunchKernelGGL(grouped_kernel(tile, all_aligned), dim3(grid), dim3(256), 0, s, start, stop, 0, d_probs, G,
+    hipExtLaunchKernelGGL(grouped_kernel(tile, all_aligned), dim3(grid), dim3(grouped_threads(tile, all_aligned)), 0, s,
+                          start, stop, 0, d_probs, G,
                           total_tiles, c_dtype == SG_BF16 ? 1 : 0, d_counters);
     SG_HIP(hipGetLastError());
     return SG_OK;

@@ -41,8 +41,14 @@ struct sg_ctx {
                                       // an event is never used both ways
     // concurrent execution of split plans: the pieces of a plan without K pieces go to these
     // streams (default priority), forked from and joined back into the caller's stream
-    int concurrent_splits = 0;    // 0 off, 1 concurrent, 2 sequential timed like 1
+    int concurrent_splits = 0;    // 0 off, 1 concurrent streams, 2 sequential timed like 1,
+                                  // 3 one persistent grouped launch of the pieces
     std::vector<hipStream_t> aux;
+    // mode 3: the pieces' descriptors (host copy, device copy) and the queue counters
+    std::vector<GroupProblem> gp_host;
+    GroupProblem* gp_dev = nullptr;
+    int gp_cap = 0;
+    int* gp_counters = nullptr;
     // accounting of the most recent sweep (timed runs only)
     std::vector<int64_t> acct_launches;
     std::vector<double> acct_seconds;
@@ -342,6 +348,59 @@ int run_concurrent(sg_ctx* ctx, const Problem& pr, const std::vector<Leaf>& leav
     return SG_OK;
 }
 
+// Mode 3: the tile shape shared by every piece of a concurrent plan when they can all run in
+// one grouped launch (no split-K or stream-K piece, no addend, a tile the grouped kernel
+// carries), else -1.
+int grouped_pieces_tile(const Problem& pr, const std::vector<Leaf>& leaves) {
+    if (pr.beta || pr.mem_only || !plan_is_concurrent(leaves)) return -1;
+    const int t = variant_tile(leaves[0].variant);
+    for (const Leaf& L : leaves)
+        if (variant_is_sk(L.variant) || variant_splits(L.variant) != 1 || variant_tile(L.variant) != t)
+            return -1;
+    return t < kNumGroupTiles ? t : -1;
+}
+
+// Mode 3: enqueue the pieces as one persistent grouped launch of tile t: descriptors built on
+// the host and copied (from pageable memory, so the host copy is free again when the call
+// returns) to a device buffer the context keeps, then the grouped kernel.
+int run_grouped_pieces(sg_ctx* ctx, const Problem& pr, const std::vector<Leaf>& leaves, int t, hipStream_t s) {
+    const int G = (int)leaves.size();
+    if (G > ctx->gp_cap) {
+        if (ctx->gp_dev) {
+            SG_HIP(hipDeviceSynchronize());         // queued launches may still read the old buffer
+            SG_HIP(hipFree(ctx->gp_dev));
+            ctx->gp_dev = nullptr;
+            ctx->gp_cap = 0;
+        }
+        SG_HIP(hipMalloc(&ctx->gp_dev, sizeof(GroupProblem) * (size_t)G));
+        ctx->gp_cap = G;
+    }
+    if (!ctx->gp_counters) {
+        SG_HIP(hipMalloc(&ctx->gp_counters, 2 * sizeof(int)));
+        SG_HIP(hipMemset(ctx->gp_counters, 0, 2 * sizeof(int)));   // every launch returns them to zero
+    }
+    const size_t esz = pr.c_bf16 ? 2 : 4;
+    std::vector<sg_problem> probs(G);
+    for (int i = 0; i < G; ++i) {
+        const Leaf& L = leaves[i];
+        probs[i] = sg_problem{L.m, L.n, L.k, pr.A + L.m0 * pr.lda + L.k0, pr.lda, pr.B + L.k0 * pr.ldb + L.n0,
+                              pr.ldb, (char*)pr.C + (L.m0 * pr.ldc + L.n0) * esz, pr.ldc};
+    }
+    ctx->gp_host.resize(G);
+    std::vector<int> order(G);
+    int total = 0, grid = 0;
+    double fl = 0.0;
+    bool aa = false;
+    int rc = grouped_fill(probs.data(), G, t, pr.c_bf16 ? SG_BF16 : SG_F32, true, ctx->gp_host.data(), order.data(),
+                          &total, &fl, &aa);
+    if (rc) return rc;
+    rc = grouped_grid(t, aa, ctx->device, total, 0, &grid);
+    if (rc) return rc;
+    SG_HIP(hipMemcpyAsync(ctx->gp_dev, ctx->gp_host.data(), sizeof(GroupProblem) * (size_t)G, hipMemcpyHostToDevice, s));
+    return grouped_enqueue(t, aa, ctx->gp_dev, G, total, grid, pr.c_bf16 ? SG_BF16 : SG_F32, ctx->gp_counters, s,
+                           nullptr, nullptr);
+}
+
 // One call.  fixed_ws != nullptr: run in that caller-provided scratch of fixed_cap bytes
 // instead of the context's workspace (no allocation, pieces always one after another); a plan
 // that needs more gives SG_ERANGE before anything is enqueued.
@@ -379,6 +438,10 @@ int gemm_impl(sg_ctx* ctx, const sg_gemm_args* a, hipStream_t s, std::vector<Lea
             if (rc) return rc;
         }
         return SG_OK;
+    }
+    if (ctx->concurrent_splits == 3) {
+        const int t = grouped_pieces_tile(pr, leaves);
+        if (t >= 0) return run_grouped_pieces(ctx, pr, leaves, t, s);
     }
     if (ctx->concurrent_splits == 1 && plan_is_concurrent(leaves)) {
         std::vector<size_t> offs;
@@ -488,6 +551,9 @@ int sg_ctx_destroy(sg_ctx* ctx) {
         note(hipStreamSynchronize(st), "hipStreamSynchronize");
         note(hipStreamDestroy(st), "hipStreamDestroy");
     }
+    if (ctx->gp_dev || ctx->gp_counters) note(hipDeviceSynchronize(), "hipDeviceSynchronize");
+    if (ctx->gp_dev) note(hipFree(ctx->gp_dev), "hipFree");
+    if (ctx->gp_counters) note(hipFree(ctx->gp_counters), "hipFree");
     for (hipEvent_t e : ctx->events) note(hipEventDestroy(e), "hipEventDestroy");
     for (hipEvent_t e : ctx->marks) note(hipEventDestroy(e), "hipEventDestroy");
     if (ctx->ws) {
@@ -507,7 +573,7 @@ int sg_ctx_set_plain_variant(sg_ctx* ctx, int variant) {
 }
 
 int sg_ctx_set_concurrent_splits(sg_ctx* ctx, int on) {
-    if (!ctx || on < 0 || on > 2) return fail(SG_EINVAL, "bad argument");
+    if (!ctx || on < 0 || on > 3) return fail(SG_EINVAL, "bad argument");
     ctx->concurrent_splits = on;
     return SG_OK;
 }
@@ -793,9 +859,11 @@ int time_plan_concurrent(sg_ctx* ctx, const Problem& pr, const std::vector<Leaf>
     const size_t per = 2 + ns;                     // fork, joins, end marker
     rc = ensure_marks(ctx, per * (size_t)reps);
     if (rc) return rc;
+    const int gt = ctx->concurrent_splits == 3 ? grouped_pieces_tile(pr, leaves) : -1;
     auto run = [&](size_t b) -> int {
         if (ctx->concurrent_splits == 1) return run_concurrent(ctx, pr, leaves, offs, s, ctx->marks[b], &ctx->marks[b + 1]);
         SG_HIP(hipEventRecord(ctx->marks[b], s));
+        if (gt >= 0) return run_grouped_pieces(ctx, pr, leaves, gt, s);
         for (size_t i = 0; i < leaves.size(); ++i) {
             int e = run_leaf(pr, leaves[i], ctx->ws, offs[i], s);
             if (e) return e;

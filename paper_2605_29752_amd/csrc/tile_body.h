@@ -79,14 +79,15 @@ constexpr int smem_elems() { return 2 * (BM + BN) * LDK; }
 // its four consecutive columns of one row straight from the accumulators, 8 bytes (BF16) or
 // 16 bytes (FP32) per fragment, with no LDS round trip.  Returns false (nothing stored) when
 // the tile does not qualify.
-template <int BM, int BN>
+template <int BM, int BN, int NW = 4>
 __device__ __forceinline__ bool epilogue_direct(const KArgs& p, const int m0, const int n0, const int kz,
-                                                const f32x4_t (&acc)[BM / 32][BN / 32]) {
+                                                const f32x4_t (&acc)[BM / 32][BN / (8 * NW)]) {
     if (!(m0 + BM <= p.M && n0 + BN <= p.N && p.vec_ok && p.add_kind == ADD_NONE)) return false;
-    constexpr int WM = BM / 2, WN = BN / 2;
+    constexpr int NWN = NW / 2;
+    constexpr int WM = BM / 2, WN = BN / NWN;
     constexpr int FM = WM / 16, FN = WN / 16;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int wm = wave >> 1, wn = wave & 1;
+    const int wm = wave / NWN, wn = wave % NWN;
     const int lr = lane & 15, lg = lane >> 4;
     const int64_t row0 = (int64_t)(m0 + wm * WM + lr);
     const int col0 = n0 + wn * WN + 4 * lg;
@@ -118,15 +119,16 @@ __device__ __forceinline__ bool epilogue_direct(const KArgs& p, const int m0, co
 // stages are free), then writes the band out row by row: lanes cover 4 consecutive columns
 // each, so a wave stores whole row segments.  acc[i][j] holds rows 16 i + (lane % 16) and
 // columns 16 j + 4 (lane / 16) .. + 3 of the wave's sub-tile.
-template <int BM, int BN>
+template <int BM, int BN, int NW = 4>
 __device__ __forceinline__ void epilogue(const KArgs& p, const int m0, const int n0, const int kz,
                                          uint16_t* __restrict__ smem,
-                                         const f32x4_t (&acc)[BM / 32][BN / 32]) {
-    constexpr int WM = BM / 2, WN = BN / 2;
+                                         const f32x4_t (&acc)[BM / 32][BN / (8 * NW)]) {
+    constexpr int NWN = NW / 2;                           // waves along N (2 along M)
+    constexpr int WM = BM / 2, WN = BN / NWN;
     constexpr int FM = WM / 16, FN = WN / 16;
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
-    const int wm = wave >> 1, wn = wave & 1;
+    const int wm = wave / NWN, wn = wave % NWN;
     const int lr = lane & 15, lg = lane >> 4;
     constexpr int EPAD = WN + 4;                          // f32 row of the band, padded
     float* band = (float*)smem + wave * 16 * EPAD;

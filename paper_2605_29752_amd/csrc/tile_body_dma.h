@@ -1,7 +1,7 @@
 // Tile body with direct-to-LDS operand loads (aligned fast path).
 //
-// The same tile as tile_body.h (256 threads, 2 x 2 waves, MFMA 16x16x32 BF16, B^T as the
-// first MFMA operand, LDS-staged epilogue), but the operands travel HBM -> LDS with
+// The same tile as tile_body.h (2 x 2 or 2 x 4 waves of 64 lanes, MFMA 16x16x32 BF16, B^T as
+// the first MFMA operand, LDS-staged epilogue), but the operands travel HBM -> LDS with
 // `buffer_load_dwordx4 ... lds`: no staging registers, so the loads of later K stages are in
 // flight while a stage is multiplied, in a ring of LDS stages.  Stage depth BKD (32 or 64 of K,
 // one or two MFMA K steps) and ring depth are chosen per tile (DmaTile).
@@ -26,7 +26,8 @@
 
 namespace sg {
 
-template <int BM, int BN, bool DEEP = false>
+// NW: waves per work-group, 4 (a 2 x 2 grid) or 8 (2 x 4: two waves on every SIMD).
+template <int BM, int BN, bool DEEP = false, int NW = 4>
 struct DmaTile {
     // Stage depth and ring depth per tile, from measurements (4096^3, TFLOP/s):
     //  * tiles up to 128 x 128: 64-deep stages (two MFMA K steps per barrier) in a two-stage ring;
@@ -50,11 +51,12 @@ struct DmaTile {
     static constexpr int A_BYTES = BM * BKD * 2;
     static constexpr int B_BYTES = BKD * BN * 2;
     static constexpr int STAGE_BYTES = A_BYTES + B_BYTES;
-    static constexpr int A_INSTR = A_BYTES / 1024 / 4;   // DMA instructions per wave per stage
-    static constexpr int B_INSTR = B_BYTES / 1024 / 4;
+    static constexpr int A_INSTR = A_BYTES / 1024 / NW;  // DMA instructions per wave per stage
+    static constexpr int B_INSTR = B_BYTES / 1024 / NW;
     static constexpr int B_ROWS_PER_INSTR = 512 / BN;    // 1 KiB = 512 BF16
     static constexpr int B_CHUNKS = BN / 8;              // 16-byte chunks per B row
     static constexpr int LDS_BYTES = STAGES * STAGE_BYTES;
+    static_assert(NW == 4 || NW == 8, "2 x 2 or 2 x 4 waves");
     static_assert(A_INSTR >= 1 && B_INSTR >= 1 && B_CHUNKS >= 8, "tile shape");
     static_assert(STAGES >= 2 && STAGES <= 4, "the main loop's waits cover at most two later steps");
     // A split-K range is a multiple of kBK long and a stage must not run past its end: the
@@ -62,10 +64,23 @@ struct DmaTile {
     static_assert((DEEP ? kDeepBK : kBK) % BKD == 0, "a K stage would straddle two split-K ranges");
 };
 
-template <int BM, int BN, bool DEEP = false>
+// Waves per work-group of the direct-to-LDS kernels that run one tile shape per launch: eight
+// (2 x 4) for the 256-wide tiles, four (2 x 2) for the rest.  One wave on a SIMD draws LDS
+// fragment reads at about 32 bytes per clock (a probe of conflict-free ds_read_b128 with eight
+// reads in flight: 131 bytes per clock per CU with four waves, 262 with eight), so a wave that
+// both reads its fragments and issues its MFMAs stalls on the reads; with two waves per SIMD one
+// multiplies while the other reads.  Measured against four waves (TFLOP/s): 256 x 256 at 4096^3
+// 976 -> 1,063 and at 4096 x 4096 x 1024 680 -> 785; 128 x 256 1,148 -> 1,205 at 4096^3 and
+// +15-29 % on mid-size shapes (2048^3 307 -> 384); 256 x 128 1,102 -> 1,151.  The 128 x 128 tile
+// gains on mid-size shapes (1024^3 149 -> 179) but loses 4-10 % on the large ones, where the
+// landscape spends most of its time in it, and the 64-wide tiles lose: they stay at four.
+template <int BM, int BN>
+constexpr int call_waves() { return (BM * BN >= 128 * 256) ? 8 : 4; }
+
+template <int BM, int BN, bool DEEP = false, int NW = 4>
 constexpr int dma_smem_bytes() {
-    constexpr int ring = DmaTile<BM, BN, DEEP>::LDS_BYTES;
-    constexpr int epi = 4 * 16 * (BN / 2 + 4) * 4;
+    constexpr int ring = DmaTile<BM, BN, DEEP, NW>::LDS_BYTES;
+    constexpr int epi = NW * 16 * (BN / (NW / 2) + 4) * 4;   // one staged 16-row band per wave
     return ring > epi ? ring : epi;
 }
 
@@ -122,17 +137,18 @@ __device__ __forceinline__ void dma16(const i32x4_t rsrc, uint32_t voffset, uint
 // same operand loads into the same ring, the same waits and barriers, and the same stores of C,
 // with the fragment reads and the matrix-core products left out (C is written as zeros, plus
 // the addend if one is fused).
-template <int BM, int BN, bool MEM = false, bool DEEP = false>
+template <int BM, int BN, bool MEM = false, bool DEEP = false, int NW = 4>
 __device__ __forceinline__ void tile_body_dma_range(const KArgs& p, const int m0, const int n0, const int kz,
                                                     const int kb, const int ke, uint16_t* __restrict__ smem) {
-    using T = DmaTile<BM, BN, DEEP>;
-    constexpr int WM = BM / 2, WN = BN / 2;
+    using T = DmaTile<BM, BN, DEEP, NW>;
+    constexpr int NWN = NW / 2;                          // waves along N (2 along M)
+    constexpr int WM = BM / 2, WN = BN / NWN;
     constexpr int FM = WM / 16, FN = WN / 16;
     constexpr int PER_STAGE = T::A_INSTR + T::B_INSTR;  // vmcnt units per stage per lane
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
-    const int wm = wave >> 1, wn = wave & 1;
+    const int wm = wave / NWN, wn = wave % NWN;
     const int lr = lane & 15, lg = lane >> 4;
 
     const int nk = (ke - kb + T::BKD - 1) / T::BKD;
@@ -324,17 +340,17 @@ __device__ __forceinline__ void tile_body_dma_range(const KArgs& p, const int m0
     // raise them past 256 VGPRs and halve their occupancy.  A caller that runs tiles back to
     // back must put a barrier before the next tile's loads, as the persistent kernel does.
     if constexpr (T::SMALL)
-        if (epilogue_direct<BM, BN>(p, m0, n0, kz, acc)) return;
+        if (epilogue_direct<BM, BN, NW>(p, m0, n0, kz, acc)) return;
     __syncthreads();                            // ring no longer read: the epilogue reuses it
-    epilogue<BM, BN>(p, m0, n0, kz, smem, acc);
+    epilogue<BM, BN, NW>(p, m0, n0, kz, smem, acc);
 }
 
 // One tile over the K range of split kz: [kz k_chunk, min(Kl, (kz + 1) k_chunk)).
-template <int BM, int BN, bool MEM = false, bool DEEP = false>
+template <int BM, int BN, bool MEM = false, bool DEEP = false, int NW = 4>
 __device__ __forceinline__ void tile_body_dma(const KArgs& p, const int m0, const int n0, const int kz,
                                               uint16_t* __restrict__ smem) {
     const int kb = kz * p.k_chunk;
-    tile_body_dma_range<BM, BN, MEM, DEEP>(p, m0, n0, kz, kb, min(p.Kl, kb + p.k_chunk), smem);
+    tile_body_dma_range<BM, BN, MEM, DEEP, NW>(p, m0, n0, kz, kb, min(p.Kl, kb + p.k_chunk), smem);
 }
 
 }  // namespace sg
