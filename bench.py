@@ -9,8 +9,10 @@ ldb = N).
 Set-up (untimed): measure T0 for every variant of the tile family at every shape (randomized
 order, warm-ups, one discarded and `reps` timed launches per shape), then build the dispatch
 table (best-of-N, T1 pad, T2 split + pad).
-Timed step: one pass over all 32,768 shapes executed through the dispatch table (each shape:
-one untimed run, then `reps` timed runs of its plan), in the same randomized order.
+Timed step: one run of every one of the 32,768 shapes' plans, executed through the dispatch
+table.  The steps are taken in passes over the shapes in the same randomized order, each pass
+giving a shape one untimed run and then `reps` consecutive timed runs of its plan (the table's
+own protocol), so `steps` = 20 is four passes.
 
 Prints one JSON line: mean TFLOPs over the 32,768 shapes of the executed smoothed stack, with
 roughness and the other stacks (plain single tile, best-of-N, DP as predicted by the table)
@@ -34,7 +36,8 @@ PEAK_BF16_TFLOPS = 2516.6       # MI355X dense BF16 MFMA (256 CUs x 4096 FLOP/cl
 # forward selection of best-of-set mean TFLOPs over a seeded sample of 1,024 landscape cells with
 # every variant timed (all 28 reached 476.0 there, these 13 475.8), plus the deep-K 64x64 tile
 # without split and with 2 and 4 splits, which win shapes with few tiles (1024^3: 264 against
-# 213; 1024 x 1024 x 4096: 411 against 381).  256x256 (variant 0) is the plain stack.
+# 213; 1024 x 1024 x 4096: 411 against 381).  256x256 (variant 0) is the paper's default tile,
+# reported beside the plain stack.
 DEFAULT_VARIANTS = "0,4,8,12,13,14,16,20,21,22,24,26,27,28,29,30"
 
 
@@ -847,9 +850,12 @@ def run_offgrid(args, sg, torch, ctx, stream):
 
 def run_serve(args, sg, torch, ctx, table=None):
     """Config 5: Poisson requests over four transformer-layer weights (the full duration), grouped
-    continuous batching versus per-request dispatch, same arrivals and tile classes (M <= 64 on
-    the small tile, the rest on the main tile); then each mode at saturation, closed loop with a
-    fixed number of requests outstanding."""
+    continuous batching versus per-request dispatch on the same four stream slots, same arrivals
+    and tile classes (M <= 64 on the small tile, the rest on the main tile).  Then saturation,
+    closed loop with a fixed number of requests outstanding: grouped, per-request on four slots,
+    per-call dispatch on one stream (each request launched alone, in order, as a caller looping
+    over gemm calls would), and the same grouped / per-request pair on a skinny mix (M <= 64,
+    where launches rather than matrix work bound the throughput)."""
     shapes = [(4096, 4096), (4096, 11008), (11008, 4096), (4096, 14336)]     # (K, N)
     ws = []
     for i, (K, N) in enumerate(shapes):
@@ -859,32 +865,53 @@ def run_serve(args, sg, torch, ctx, table=None):
     torch.cuda.synchronize()
     out = {"rate_req_s": args.serve_rate, "duration_s": args.serve_seconds,
            "warmup_s": args.serve_warmup, "tile": sg.variant_info(4 * args.serve_tile).name[:-6],
-           "small_m": args.serve_small_m, "small_tile": sg.variant_info(4 * args.serve_small_tile).name[:-6]}
+           "small_m": args.serve_small_m, "small_tile": sg.variant_info(4 * args.serve_small_tile).name[:-6],
+           "solo_m": args.serve_solo_m}
+
+    def server(mode, slots):
+        return sg.Server(ctx, [(K, N, t.data_ptr(), N) for (K, N), t in zip(shapes, ws)],
+                         hbm_budget=args.serve_budget_gb << 30, max_inflight=slots, max_group=64,
+                         mode=mode, tile=args.serve_tile, max_m=8192, seed=5,
+                         small_m=args.serve_small_m, small_tile=args.serve_small_tile,
+                         solo_m=args.serve_solo_m if mode == sg.SERVE_GROUPED else 0)
+
+    sat = args.serve_saturate
     for name, mode in (("grouped", sg.SERVE_GROUPED), ("per_request", sg.SERVE_PER_REQUEST)):
-        srv = sg.Server(ctx, [(K, N, t.data_ptr(), N) for (K, N), t in zip(shapes, ws)],
-                        hbm_budget=args.serve_budget_gb << 30, max_inflight=4, max_group=64,
-                        mode=mode, tile=args.serve_tile, max_m=8192, seed=5,
-                        small_m=args.serve_small_m, small_tile=args.serve_small_tile)
+        srv = server(mode, 4)
         try:
             log("serving (%s) %.0f req/s for %.0f s" % (name, args.serve_rate, args.serve_seconds))
             rep = srv.serve_poisson(args.serve_rate, args.serve_seconds, args.serve_warmup, 5, 8192)
             out[name] = rep
             log("  p50 %.2f ms p99 %.2f ms, %.1f req/s, %.1f TFLOP/s, %d launches"
                 % (rep["p50_ms"], rep["p99_ms"], rep["req_per_s"], rep["tflops"], rep["launches"]))
-            if args.serve_saturate > 0:
-                sat = srv.serve_closed(args.serve_outstanding, args.serve_saturate, min(2.0, args.serve_saturate / 4),
-                                       7, 8192)
-                out[name + "_saturated"] = sat
-                log("  saturated (%d outstanding): %.1f req/s, %.1f TFLOP/s, p50 %.2f ms p99 %.2f ms, %d launches"
-                    % (args.serve_outstanding, sat["req_per_s"], sat["tflops"], sat["p50_ms"], sat["p99_ms"],
-                       sat["launches"]))
+            if sat > 0:
+                for tag, max_m in (("saturated", 8192), ("saturated_skinny", 64)):
+                    r = srv.serve_closed(args.serve_outstanding, sat, min(2.0, sat / 4), 7, max_m)
+                    out[name + "_" + tag] = r
+                    log("  %s (%d outstanding, M <= %d): %.1f req/s, %.1f TFLOP/s, p50 %.2f ms p99 %.2f ms, "
+                        "%d launches" % (tag, args.serve_outstanding, max_m, r["req_per_s"], r["tflops"],
+                                         r["p50_ms"], r["p99_ms"], r["launches"]))
         finally:
             srv.close()
-    if args.serve_saturate > 0:
-        g, p = out["grouped_saturated"], out["per_request_saturated"]
-        out["saturation"] = {"outstanding": args.serve_outstanding, "seconds": args.serve_saturate,
-                             "throughput_ratio": g["req_per_s"] / p["req_per_s"] if p["req_per_s"] else None,
-                             "p99_ratio": g["p99_ms"] / p["p99_ms"] if p["p99_ms"] else None}
+    if sat > 0:
+        srv = server(sg.SERVE_PER_REQUEST, 1)
+        try:
+            r = srv.serve_closed(args.serve_outstanding, sat, min(2.0, sat / 4), 7, 8192)
+            out["per_call_one_stream_saturated"] = r
+            log("  per-call, one stream (%d outstanding): %.1f req/s, %.1f TFLOP/s, p50 %.2f ms p99 %.2f ms"
+                % (args.serve_outstanding, r["req_per_s"], r["tflops"], r["p50_ms"], r["p99_ms"]))
+        finally:
+            srv.close()
+
+        def ratio(a, b):
+            return {"throughput_ratio": a["req_per_s"] / b["req_per_s"] if b["req_per_s"] else None,
+                    "p99_ratio": a["p99_ms"] / b["p99_ms"] if b["p99_ms"] else None}
+        g = out["grouped_saturated"]
+        out["saturation"] = {"outstanding": args.serve_outstanding, "seconds": sat,
+                             "grouped_vs_per_request_4_slots": ratio(g, out["per_request_saturated"]),
+                             "grouped_vs_per_call_one_stream": ratio(g, out["per_call_one_stream_saturated"]),
+                             "skinny_grouped_vs_per_request_4_slots": ratio(out["grouped_saturated_skinny"],
+                                                                            out["per_request_saturated_skinny"])}
     del ws
     return out
 
@@ -898,7 +925,8 @@ def main():
                     help="timed runs per shape in the table measurement (one more is discarded), and "
                          "the least number of timed runs per shape over all timed passes")
     ap.add_argument("--reps-per-pass", type=int, default=0,
-                    help="timed runs per shape in each timed pass (0: ceil(reps / steps))")
+                    help="timed runs per shape in each timed pass (0: reps); the timed steps are "
+                         "taken in passes of this many consecutive runs per shape")
     ap.add_argument("--budget", type=float, default=560.0,
                     help="wall-clock seconds the default run aims to finish in: the grouped and "
                          "serving legs are skipped (and named in the output) when they would not fit")
@@ -935,7 +963,9 @@ def main():
     ap.add_argument("--serve-tile", type=int, default=3)
     ap.add_argument("--serve-small-m", type=int, default=64)
     ap.add_argument("--serve-small-tile", type=int, default=6)
-    ap.add_argument("--serve-saturate", type=float, default=12.0,
+    ap.add_argument("--serve-solo-m", type=int, default=1024,
+                    help="grouped serving launches requests with M above this on their own (0: never)")
+    ap.add_argument("--serve-saturate", type=float, default=8.0,
                     help="seconds of closed-loop saturation per serving mode (0: skip)")
     ap.add_argument("--serve-outstanding", type=int, default=64)
     ap.add_argument("--serve-budget-gb", type=int, default=64)
@@ -1127,10 +1157,13 @@ def main():
     cells = rng.permutation(n ** 3)
     idx = np.array(np.unravel_index(cells, (n, n, n))).T
     shapes = [(int((i + 1) * step), int((j + 1) * step), int((k + 1) * step)) for i, j, k in idx]
-    # timed launches per shape per pass: enough that the timed passes together give every shape
-    # at least `reps` timed runs (each run after one untimed run of the same shape, as in the
-    # table's protocol)
-    reps_pass = args.reps_per_pass or max(1, -(-args.reps // max(args.steps, 1)))
+    # A step is one timed run of every shape's plan.  The steps are taken in passes of
+    # `reps_pass` consecutive runs per shape, each pass after one untimed run of the shape --
+    # the table's own protocol (one discarded launch, then `reps` timed ones), so executed and
+    # tabulated times are measured alike (a lone timed launch after the discarded one reads
+    # 13-17 % slower on small shapes than the mean of five).
+    reps_pass = max(1, min(args.reps_per_pass or args.reps, args.steps))
+    pass_reps = [reps_pass] * (args.steps // reps_pass) + ([args.steps % reps_pass] if args.steps % reps_pass else [])
 
     def one_pass(mode=sg.MODE_DP, variant=0, reps=reps_pass, interval=False):
         ctx.set_interval_timing(interval)
@@ -1145,31 +1178,31 @@ def main():
 
     for w in range(args.warmup):
         log("warm-up pass %d" % w)
-        one_pass()
+        one_pass(reps=1)
     torch.cuda.synchronize()
     passes = []
     launches = np.zeros(sg.num_variants(), dtype=np.int64)
     ksec = np.zeros(sg.num_variants())
     kflops = np.zeros(sg.num_variants())
     t0 = time.perf_counter()
-    for s_ in range(args.steps):
-        sec, _ = one_pass()
+    for s_, r_ in enumerate(pass_reps):
+        sec, _ = one_pass(reps=r_)
         la, se, fl = ctx.kernel_times()
         launches += la
         ksec += se
         kflops += fl
         passes.append(to_grid(sec))
-        log("timed pass %d done (%.0f s since start)" % (s_, elapsed()))
+        log("timed pass %d (%d runs per shape) done (%.0f s since start)" % (s_, r_, elapsed()))
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms_per_step = wall / args.steps * 1e3
-    exec_sec = np.mean(passes, axis=0)
+    exec_sec = np.average(passes, axis=0, weights=pass_reps)
     # gap-included executions: every run of the DP plans and of the plain variant timed as a
-    # whole between two stream markers (one pass each, three marker-timed runs per shape)
+    # whole between two stream markers (one pass each, `reps` marker-timed runs per shape)
     log("interval-timed passes (DP plans, plain %s)" % sg.variant_info(plain_variant).name)
-    _, iv = one_pass(reps=3, interval=True)
+    _, iv = one_pass(reps=args.reps, interval=True)
     exec_iv = to_grid(iv)
-    _, p_iv = one_pass(sg.MODE_VARIANT, plain_variant, 3, interval=True)
+    _, p_iv = one_pass(sg.MODE_VARIANT, plain_variant, args.reps, interval=True)
     plain_exec_iv = to_grid(p_iv)
 
     M3 = sizes[:, None, None]
@@ -1202,17 +1235,19 @@ def main():
     # difference of consecutive passes, scaled by 1/sqrt 2), and what is left of it in the
     # mean of all passes (1/sqrt(passes) of that)
     noise = {}
-    if len(passes) >= 2:
-        tfp = [W3 / p / 1e12 for p in passes]
+    full = [p for p, r_ in zip(passes, pass_reps) if r_ == reps_pass]
+    if len(full) >= 2:
+        tfp = [W3 / p / 1e12 for p in full]
         single = [sg.landscape_stats((tfp[i] - tfp[i + 1]) / np.sqrt(2.0)) for i in range(len(tfp) - 1)]
         r1 = float(np.mean([x["roughness_3d"] for x in single]))
         sl1 = float(np.mean([np.mean([sg.roughness(row) for row in ((tfp[i] - tfp[i + 1]) / np.sqrt(2.0))[:, :, -1]])
                              for i in range(len(tfp) - 1)]))
-        cv = float(np.median(np.std(np.array(passes), axis=0) / exec_sec))
+        cv = float(np.median(np.std(np.array(full), axis=0) / np.mean(full, axis=0)))
+        # (a shorter remainder pass, if any, is left out of these estimates)
         noise = {"single_pass_roughness_3d": r1, "single_pass_roughness_slice": sl1,
-                 "mean_of_passes_roughness_3d": r1 / np.sqrt(len(passes)),
-                 "mean_of_passes_roughness_slice": sl1 / np.sqrt(len(passes)),
-                 "median_cv_across_passes": cv, "passes": len(passes), "timed_runs_per_shape_per_pass": reps_pass}
+                 "mean_of_passes_roughness_3d": r1 / np.sqrt(len(full)),
+                 "mean_of_passes_roughness_slice": sl1 / np.sqrt(len(full)),
+                 "median_cv_across_passes": cv, "passes": len(full), "timed_runs_per_shape_per_pass": reps_pass}
 
     # dominant kernel: the tile kernel with the most execution time, over every variant that
     # launches it (the split-K variants of a tile run the same kernel; their accounted time is
@@ -1309,7 +1344,7 @@ def main():
             skipped.append("grouped")
     ctx.set_table(None)
     if not args.no_serve:
-        need = 2 * (args.serve_seconds + args.serve_saturate + 15)
+        need = 2 * (args.serve_seconds + 2 * args.serve_saturate + 10) + args.serve_saturate + 5
         if elapsed() + need < args.budget:
             srv = run_serve(args, sg, torch, ctx, table)
             result["served_p50_ms"] = srv["grouped"]["p50_ms"]

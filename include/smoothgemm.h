@@ -392,6 +392,8 @@ int sg_graph_destroy(sg_graph* graph);
  * as one grouped kernel on any free stream slot, so new work overlaps running work.  Every
  * request belongs to a tile class (small_tile for M <= small_m, else tile); a launch takes the
  * oldest admitted request and up to max_group - 1 admitted requests after it of its class.  A
+ * request with M > solo_m (solo_m > 0) is launched on its own even in grouped mode: it fills the
+ * device by itself, and in a group it would only wait for the group's other members.  A
  * launch of one request runs the tile kernel directly (no descriptors, no work queue).
  * SG_SERVE_PER_REQUEST launches every request on its own (the per-call baseline), with the same
  * tile classes.  Times are
@@ -415,6 +417,7 @@ typedef struct sg_server_cfg {
     double a_scale;             /* activation standard deviation                                 */
     int64_t small_m;            /* requests with M <= small_m run with small_tile (0: none)      */
     int small_tile;             /* tile shape index 0..6 for those skinny requests               */
+    int64_t solo_m;             /* requests with M > solo_m launch alone (0: every request groups) */
 } sg_server_cfg;
 typedef struct sg_request { uint64_t id; int64_t M; int weight; } sg_request;
 typedef struct sg_completion {
@@ -424,6 +427,7 @@ typedef struct sg_completion {
     int status;                 /* SG_OK or the failure code                                     */
     int64_t a_offset;           /* element offset of A in the activation pool                    */
     int tile;                   /* tile shape the request ran with                               */
+    int group_size;             /* requests in the launch that ran it (1: launched alone)        */
     double t_arrival, t_admit, t_launch, t_done;
     const void* A;              /* device; valid until release when keep_results, else NULL      */
     const void* C;

@@ -84,6 +84,8 @@ struct Req {
     int64_t M = 0;
     int w = 0;
     int tile = 0;             // tile shape this request runs with (its class)
+    bool solo = false;        // launched on its own even in grouped mode
+    int group = 0;            // requests in the launch that ran it
     int64_t a_offset = 0;     // element offset of A in the activation pool
     size_t offA = 0, offC = 0, bytesA = 0, bytesC = 0;
     double t_arr = 0, t_adm = 0, t_launch = 0, t_done = 0;
@@ -147,6 +149,7 @@ void fill_completion(const sg_server* sv, const Req& r, sg_completion* c) {
     c->status = r.status;
     c->a_offset = r.a_offset;
     c->tile = r.tile;
+    c->group_size = r.group;
     c->t_arrival = r.t_arr;
     c->t_admit = r.t_adm;
     c->t_launch = r.t_launch;
@@ -217,7 +220,8 @@ bool worker_pass(sg_server* sv) {
     // 3. launch onto free slots: a group is the oldest admitted request and the admitted
     //    requests after it of the same tile class (every launch runs one tile shape), oldest
     //    first, at most an equal share of the admitted requests per free slot, so that work
-    //    admitted together spreads over the free slots and runs side by side
+    //    admitted together spreads over the free slots and runs side by side.  A solo request
+    //    is a group of its own and is never added to another request's group.
     int free_slots = 0;
     for (const Slot& sl : sv->slots) free_slots += sl.busy ? 0 : 1;
     for (Slot& sl : sv->slots) {
@@ -229,10 +233,12 @@ bool worker_pass(sg_server* sv) {
             const int cap = sv->cfg.mode == SG_SERVE_GROUPED ? std::max(1, std::min(sv->cfg.max_group, share)) : 1;
             --free_slots;
             if (!sv->admitted.empty()) {
-                const int cls = sv->reqs[sv->admitted.front()].tile;
-                for (auto it = sv->admitted.begin(); it != sv->admitted.end() && (int)group.size() < cap;) {
+                const Req& first = sv->reqs[sv->admitted.front()];
+                const int cls = first.tile;
+                const int lim = first.solo ? 1 : cap;
+                for (auto it = sv->admitted.begin(); it != sv->admitted.end() && (int)group.size() < lim;) {
                     Req& r = sv->reqs[*it];
-                    if (r.tile == cls) {
+                    if (r.tile == cls && (group.empty() || !r.solo)) {
                         group.push_back(&r);
                         it = sv->admitted.erase(it);
                     } else {
@@ -254,6 +260,7 @@ bool worker_pass(sg_server* sv) {
             probs[i] = sg_problem{r.M, w.N, w.K, sv->arena + r.offA, w.K, w.B, w.ldb,
                                   sv->arena + r.offC, w.N};
             r.t_launch = t;
+            r.group = (int)group.size();
             sl.tickets.push_back(r.ticket);
         }
         int rc = SG_OK;
@@ -330,7 +337,7 @@ int sg_server_create(sg_ctx* ctx, const sg_server_cfg* cfg, sg_server** out) {
     if (cfg->hbm_budget < (1u << 20) || cfg->max_inflight < 1 || cfg->max_inflight > 16 ||
         cfg->max_group < 1 || cfg->max_group > 4096 || cfg->queue_cap < 1 || cfg->n_weights < 1 ||
         !cfg->weights || cfg->tile < 0 || cfg->tile >= kNumGroupTiles || cfg->max_m < 1 ||
-        cfg->small_m < 0 || cfg->small_tile < 0 || cfg->small_tile >= kNumGroupTiles ||
+        cfg->small_m < 0 || cfg->small_tile < 0 || cfg->small_tile >= kNumGroupTiles || cfg->solo_m < 0 ||
         (cfg->mode != SG_SERVE_GROUPED && cfg->mode != SG_SERVE_PER_REQUEST))
         return fail(SG_EINVAL, "bad server configuration");
     int64_t maxK = 0;
@@ -396,6 +403,7 @@ int sg_server_submit(sg_server* sv, const sg_request* req, double arrival_s, uin
     r.M = req->M;
     r.w = req->weight;
     r.tile = req->M <= sv->cfg.small_m ? sv->cfg.small_tile : sv->cfg.tile;
+    r.solo = sv->cfg.solo_m > 0 && req->M > sv->cfg.solo_m;
     const int64_t span = sv->act_elems - req->M * w.K;
     r.a_offset = (int64_t)(mix64(sv->cfg.seed ^ mix64(req->id + 1)) % (uint64_t)(span / 8 + 1)) * 8;
     r.t_arr = arrival_s >= 0 ? arrival_s : now_s(sv->t0);

@@ -245,9 +245,9 @@ __device__ __forceinline__ void tile_body_dma_range(const KArgs& p, const int m0
                 for (int d = 0; d < PER_STAGE; ++d) issue_one(kt_next, slot_next, d);
       } else {
         const char* stage = (const char*)smem + slot * T::STAGE_BYTES;
-#pragma unroll
-        for (int h = 0; h < T::SUB; ++h) {
-            bf16x8_t af[FM], bfr[FN];
+        // Fragment reads of MFMA K step h of this stage: FM A fragments (one 16-byte read each)
+        // and FN B fragments (two transposing 8-byte reads each).
+        auto read_frags = [&](int h, bf16x8_t* af, bf16x8_t* bfr) {
 #pragma unroll
             for (int i = 0; i < FM; ++i) {
                 const int row = wm * WM + i * 16 + lr;
@@ -267,9 +267,8 @@ __device__ __forceinline__ void tile_body_dma_range(const KArgs& p, const int m0
                 }
                 bfr[j] = bf16x8_t{hv[0][0], hv[0][1], hv[0][2], hv[0][3], hv[1][0], hv[1][1], hv[1][2], hv[1][3]};
             }
-            // raised wave priority while the MFMAs issue, so that the waves of a CU that are
-            // ready to multiply are preferred over those issuing loads
-            __builtin_amdgcn_s_setprio(1);
+        };
+        auto mfma_step = [&](const bf16x8_t* af, const bf16x8_t* bfr, int kt_next, int slot_next, int h, bool issue_next) {
 #pragma unroll
             for (int i = 0; i < FM; ++i) {
 #pragma unroll
@@ -286,7 +285,49 @@ __device__ __forceinline__ void tile_body_dma_range(const KArgs& p, const int m0
                     __builtin_amdgcn_sched_barrier(0);
                 }
             }
-            __builtin_amdgcn_s_setprio(0);
+        };
+        if constexpr (T::SUB >= 2 && !SPREAD) {
+            // Several MFMA K steps per stage: the fragments of step h + 1 are read while the
+            // MFMAs of step h run (two fragment sets), one read after each MFMA, so that the
+            // wave's LDS read latency is hidden behind its own matrix work within a stage.
+            // Measured against reading each step's fragments just before its MFMAs (TFLOP/s,
+            // 4096^3): 128 x 128 1,052 -> 1,080, 128 x 64 825 -> 888, 64 x 128 827 -> 865,
+            // 64 x 64 716 -> 741; the 128-deep 64 x 64 at 1024 x 1024 x 4096 362 -> 373.  Only
+            // K = 128 loses (4096 x 4096 x 128 on 128 x 128: 252 -> 240).  Giving the 256-wide
+            // tiles 64-deep stages to pipeline the same way costs them their second work-group
+            // per CU (96 KiB) and measured slower at 4096^3 (128 x 256: 1,166 -> 996).
+            constexpr int NREAD = FM + 2 * FN, NMFMA = FM * FN;
+            constexpr int NPAIR = NREAD < NMFMA ? NREAD : NMFMA;
+            bf16x8_t af[2][FM], bfr[2][FN];
+            read_frags(0, af[0], bfr[0]);
+#pragma unroll
+            for (int h = 0; h < T::SUB; ++h) {
+                const int c = h & 1;
+                __builtin_amdgcn_s_setprio(1);
+                if (h + 1 < T::SUB) read_frags(h + 1, af[c ^ 1], bfr[c ^ 1]);
+                mfma_step(af[c], bfr[c], 0, 0, h, false);
+                if (h + 1 < T::SUB) {
+#pragma unroll
+                    for (int q = 0; q < NPAIR; ++q) {
+                        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);   // one MFMA
+                        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);   // one LDS read
+                    }
+                    if constexpr (NMFMA > NPAIR) __builtin_amdgcn_sched_group_barrier(0x008, NMFMA - NPAIR, 0);
+                    if constexpr (NREAD > NPAIR) __builtin_amdgcn_sched_group_barrier(0x100, NREAD - NPAIR, 0);
+                }
+                __builtin_amdgcn_s_setprio(0);
+            }
+        } else {
+#pragma unroll
+            for (int h = 0; h < T::SUB; ++h) {
+                bf16x8_t af[FM], bfr[FN];
+                read_frags(h, af, bfr);
+                // raised wave priority while the MFMAs issue, so that the waves of a CU that are
+                // ready to multiply are preferred over those issuing loads
+                __builtin_amdgcn_s_setprio(1);
+                mfma_step(af, bfr, kt_next, slot_next, h, issue_next);
+                __builtin_amdgcn_s_setprio(0);
+            }
         }
       }
     };

@@ -31,12 +31,12 @@ def weights():
     return shapes, ws, host
 
 
-def _serve_and_check(ctx, weights, mode, budget, n_req=60, max_group=8):
+def _serve_and_check(ctx, weights, mode, budget, n_req=60, max_group=8, solo_m=0):
     import torch
     shapes, ws, host = weights
     srv = sg.Server(ctx, [(K, N, t.data_ptr(), N) for (K, N), t in zip(shapes, ws)],
                     hbm_budget=budget, max_inflight=2, max_group=max_group, mode=mode, tile=3,
-                    keep_results=True, max_m=600, seed=ASEED)
+                    keep_results=True, max_m=600, seed=ASEED, solo_m=solo_m)
     rng = np.random.default_rng(1)
     for i in range(n_req):
         srv.submit(i, int(rng.integers(1, 601)), int(rng.integers(0, len(shapes))))
@@ -47,14 +47,17 @@ def _serve_and_check(ctx, weights, mode, budget, n_req=60, max_group=8):
         for c in srv.poll(256):
             A = device_bytes(c.A, c.M * c.K * 2).view(np.uint16).reshape(c.M, c.K)
             Cb = device_bytes(c.C, c.M * c.N * 2).view(np.uint16).reshape(c.M, c.N)
-            comps.append((c.M, c.N, c.K, c.weight, c.status, c.a_offset, A, Cb, c.tile))
+            comps.append((c.M, c.N, c.K, c.weight, c.status, c.a_offset, A, Cb, c.tile, c.group_size))
             srv.release(c.ticket)
     assert len(comps) == n_req and all(c[4] == 0 for c in comps)
     st = srv.stats()
     assert st["peak_bytes"] <= budget and st["completed"] == n_req
     say("mode", mode, "launches", st["launches"], "peak bytes", st["peak_bytes"])
-    for (M, N, K, w, status, a_offset, A, Cb, tile) in comps:
+    for (M, N, K, w, status, a_offset, A, Cb, tile, gsize) in comps:
         assert tile == (6 if M <= 64 else 3)
+        assert 1 <= gsize <= (max_group if mode == sg.SERVE_GROUPED else 1)
+        if solo_m and M > solo_m:
+            assert gsize == 1, 'a solo request was grouped'
         want_a = synth.f32_to_bf16_bits(synth.normal_f32(ASEED, 0, M * K, 0.02, start=a_offset)).reshape(M, K)
         assert np.array_equal(A, want_a), "staged activation differs from the seeded pool"
         # alone: the same tile shape through the per-call entry point
@@ -64,6 +67,8 @@ def _serve_and_check(ctx, weights, mode, budget, n_req=60, max_group=8):
         assert np.array_equal(sg.bf16_tensor_bits(alone), Cb), "served result differs from alone"
         check_tol(synth.bf16_bits_to_f32(Cb).astype(np.float64), A, host[w], BF16)
     srv.close()
+    st["Ms"] = [c[0] for c in comps]
+    st["group_sizes"] = [c[9] for c in comps]
     return st
 
 
@@ -71,6 +76,13 @@ def test_served_equals_alone_grouped_tight_budget(ctx, weights):
     # 3 MiB holds only a few requests at once: admission must wait for completions
     st = _serve_and_check(ctx, weights, sg.SERVE_GROUPED, 3 << 20)
     assert st["launches"] < 60
+
+
+def test_served_equals_alone_grouped_solo(ctx, weights):
+    # requests with M > 300 launch on their own; the rest still share launches
+    st = _serve_and_check(ctx, weights, sg.SERVE_GROUPED, 64 << 20, solo_m=300)
+    n_solo = sum(1 for m in st["Ms"] if m > 300)
+    assert 0 < n_solo < 60 and n_solo < st["launches"] <= 60
 
 
 def test_served_equals_alone_per_request(ctx, weights):
