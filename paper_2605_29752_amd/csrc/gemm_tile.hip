@@ -149,7 +149,9 @@ __global__ __launch_bounds__((64 * call_waves<BM, BN>())) void sg_gemm_tile_dma_
             q.ldc = BN; q.out_bf16 = 0;
             q.add = nullptr; q.add_kind = ADD_NONE; q.vec_ok = 1;
         }
-        tile_body_dma_range<BM, BN, false, false, NW>(q, m0, n0, 0, k0 * BKD, min(p.Kl, k1 * BKD), smem);
+        // (no cross-stage fragment prefetch for 256 x 256 here: its registers would spill)
+        tile_body_dma_range<BM, BN, false, false, NW, !(BM == 256 && BN == 256)>(q, m0, n0, 0, k0 * BKD,
+                                                                                 min(p.Kl, k1 * BKD), smem);
         it += k1 - k0;
     }
 }

@@ -62,7 +62,8 @@ __global__ __launch_bounds__((64 * grouped_waves<BM, BN, ALL_ALIGNED>())) void s
         a.vec_ok = q.vec_ok;
         a.a_bytes = q.a_bytes; a.b_bytes = q.b_bytes;
         if (ALL_ALIGNED || q.aligned) {
-            tile_body_dma<BM, BN, false, false, NW>(a, tm * BM, tn * BN, 0, smem);
+            // (no cross-stage fragment prefetch for 256 x 256 here: its registers would spill)
+            tile_body_dma<BM, BN, false, false, NW, !(BM == 256 && BN == 256)>(a, tm * BM, tn * BN, 0, smem);
         } else {
             if constexpr (!ALL_ALIGNED) tile_body<BM, BN>(a, tm * BM, tn * BN, 0, smem);
         }

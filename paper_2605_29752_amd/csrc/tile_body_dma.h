@@ -22,6 +22,8 @@
 // Out-of-range elements are fetched with an offset past the end of the buffer and land as zeros.
 #pragma once
 
+#include <type_traits>
+
 #include "tile_body.h"
 
 namespace sg {
@@ -43,11 +45,17 @@ struct DmaTile {
     //    2048^3 498 -> 551, 4096^3 686 -> 649).
     static_assert(!DEEP || (BM == 64 && BN == 64), "deep stages are for the 64 x 64 tile");
     static constexpr bool SMALL = BM * BN <= 128 * 128;
+    // Cross-stage fragment prefetch (the fragments of stage kt + 1 read under the MFMAs of
+    // stage kt) for 256 x 256 only.  Measured on the smaller tiles with four 32-deep stages, it
+    // lost badly (128 x 128 at 4096^3: 1,068 -> 672): their 256 MFMA cycles per stage are too
+    // few to cover a barrier per 32 of K, and the two-work-group 256 x 128 / 128 x 256 cannot
+    // hold a second fragment set within the 128 registers that two work-groups per CU allow.
+    static constexpr bool XPF = !DEEP && BM == 256 && BN == 256;
     static constexpr int BKD = DEEP ? 128 : SMALL ? 64 : 32;   // K per stage
     static constexpr int SUB = BKD / 32;                 // MFMA K steps per stage
     static constexpr int A_CH = BKD / 8;                 // 16-byte chunks per A row
     static constexpr int A_ROWS_PER_INSTR = 512 / BKD;   // 1 KiB = 512 BF16
-    static constexpr int STAGES = (BM == 256 && BN == 256) ? 4 : 2;
+    static constexpr int STAGES = XPF ? 4 : 2;
     static constexpr int A_BYTES = BM * BKD * 2;
     static constexpr int B_BYTES = BKD * BN * 2;
     static constexpr int STAGE_BYTES = A_BYTES + B_BYTES;
@@ -137,7 +145,7 @@ __device__ __forceinline__ void dma16(const i32x4_t rsrc, uint32_t voffset, uint
 // same operand loads into the same ring, the same waits and barriers, and the same stores of C,
 // with the fragment reads and the matrix-core products left out (C is written as zeros, plus
 // the addend if one is fused).
-template <int BM, int BN, bool MEM = false, bool DEEP = false, int NW = 4>
+template <int BM, int BN, bool MEM = false, bool DEEP = false, int NW = 4, bool XPF_OK = true>
 __device__ __forceinline__ void tile_body_dma_range(const KArgs& p, const int m0, const int n0, const int kz,
                                                     const int kb, const int ke, uint16_t* __restrict__ smem) {
     using T = DmaTile<BM, BN, DEEP, NW>;
@@ -226,6 +234,29 @@ __device__ __forceinline__ void tile_body_dma_range(const KArgs& p, const int m0
     for (int i = 0; i < FM; ++i)
 #pragma unroll
         for (int j = 0; j < FN; ++j) acc[i][j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+
+    // One fragment of MFMA K step h in ring slot `slot`: q < FM is A fragment q (one 16-byte
+    // read), q >= FM is B fragment q - FM (two transposing 8-byte reads).
+    auto read_frag = [&](int slot, int h, int q, bf16x8_t* af, bf16x8_t* bfr) {
+        const char* stage = (const char*)smem + slot * T::STAGE_BYTES;
+        if (q < FM) {
+            const int row = wm * WM + q * 16 + lr;
+            af[q] = *(const bf16x8_t*)(stage + row * (T::BKD * 2) + (((4 * h + lg) ^ a_swz(row)) << 4));
+        } else {
+            const int j = q - FM;
+            const int tk = 32 * h + lg * 8 + (lr >> 2);
+            const int n = wn * WN + j * 16 + 4 * (lr & 3);
+            bf16x4_t hv[2];
+#pragma unroll
+            for (int r = 0; r < 2; ++r) {
+                const int k = tk + 4 * r;
+                const int off = T::A_BYTES + k * BN * 2 + (((n >> 3) ^ b_swz(k)) << 4) + (n & 7) * 2;
+                hv[r] = __builtin_amdgcn_ds_read_tr16_b64_v4bf16(
+                    (lds_bf16x4*)((lds_char*)lds + slot * T::STAGE_BYTES + off));
+            }
+            bfr[j] = bf16x8_t{hv[0][0], hv[0][1], hv[0][2], hv[0][3], hv[1][0], hv[1][1], hv[1][2], hv[1][3]};
+        }
+    };
 
     constexpr bool SPREAD = (BM == 256 && BN == 256);
     // Multiply step `slot`; with SPREAD, the loads of step kt_next into slot_next are issued
@@ -351,7 +382,56 @@ __device__ __forceinline__ void tile_body_dma_range(const KArgs& p, const int m0
 #pragma unroll
     for (int s = 0; s < S - 1; ++s)
         if (s < nk) issue(s, s);
-    if constexpr (SPREAD) {
+    if constexpr (T::XPF && XPF_OK && !MEM) {
+        // Cross-stage fragment prefetch: the fragments of stage kt + 1 are read while the MFMAs
+        // of stage kt run (two fragment sets), so a wave never waits on LDS between stages.
+        // Stage kt + 1 must have landed for every wave before its fragments are read: the wait
+        // and barrier for it come after the first MFMA row of stage kt.  The loads of stage
+        // kt + S - 1 go into the slot of stage kt - 1, whose fragments every wave consumed in
+        // its stage kt - 1 MFMAs, before that barrier.  Measured against reading each stage's
+        // fragments after its barrier (TFLOP/s): 4096^3 1,042 -> 1,137, 3840 x 2048 x 4096
+        // 494 -> 546, 4096 x 4096 x 1024 770 -> 831, 2048^3 265 -> 291.
+        constexpr int NQ = FM + FN;
+        bf16x8_t fa[2][FM], fb[2][FN];
+        sync_step(min(S - 2, nk - 1));
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) read_frag(0, 0, q, fa[0], fb[0]);
+        auto xstep = [&](auto cc, int kt) {
+            constexpr int c = decltype(cc)::value;
+            const bool has_next = kt + 1 < nk;
+            const bool load_next = kt + S - 1 < nk;
+            __builtin_amdgcn_s_setprio(1);
+#pragma unroll
+            for (int i = 0; i < FM; ++i) {
+#pragma unroll
+                for (int j = 0; j < FN; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fb[c][j], fa[c][i], acc[i][j], 0, 0, 0);
+                __builtin_amdgcn_sched_barrier(0);
+                if (i == 0 && has_next) {
+                    __builtin_amdgcn_s_setprio(0);
+                    sync_step(min(kt + S - 2, nk - 1) - (kt + 1));
+                    __builtin_amdgcn_s_setprio(1);
+                }
+                if (has_next) {
+#pragma unroll
+                    for (int q = i * NQ / FM; q < (i + 1) * NQ / FM; ++q) read_frag((kt + 1) % S, 0, q, fa[c ^ 1], fb[c ^ 1]);
+                }
+                if (load_next) {
+#pragma unroll
+                    for (int d = i * PER_STAGE / FM; d < (i + 1) * PER_STAGE / FM; ++d)
+                        issue_one(kt + S - 1, (kt + S - 1) % S, d);
+                }
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            __builtin_amdgcn_s_setprio(0);
+        };
+        int kt = 0;
+        for (; kt + 1 < nk; kt += 2) {
+            xstep(std::integral_constant<int, 0>{}, kt);
+            xstep(std::integral_constant<int, 1>{}, kt + 1);
+        }
+        if (kt < nk) xstep(std::integral_constant<int, 0>{}, kt);
+    } else if constexpr (SPREAD) {
         // A steady-state loop (loads issued inside the MFMA sequence, no branch there) and a
         // drain without loads.
         int kt = 0;
@@ -387,11 +467,11 @@ __device__ __forceinline__ void tile_body_dma_range(const KArgs& p, const int m0
 }
 
 // One tile over the K range of split kz: [kz k_chunk, min(Kl, (kz + 1) k_chunk)).
-template <int BM, int BN, bool MEM = false, bool DEEP = false, int NW = 4>
+template <int BM, int BN, bool MEM = false, bool DEEP = false, int NW = 4, bool XPF_OK = true>
 __device__ __forceinline__ void tile_body_dma(const KArgs& p, const int m0, const int n0, const int kz,
                                               uint16_t* __restrict__ smem) {
     const int kb = kz * p.k_chunk;
-    tile_body_dma_range<BM, BN, MEM, DEEP, NW>(p, m0, n0, kz, kb, min(p.Kl, kb + p.k_chunk), smem);
+    tile_body_dma_range<BM, BN, MEM, DEEP, NW, XPF_OK>(p, m0, n0, kz, kb, min(p.Kl, kb + p.k_chunk), smem);
 }
 
 }  // namespace sg

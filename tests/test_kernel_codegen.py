@@ -16,17 +16,26 @@ CSRC = os.path.join(ROOT, "paper_2605_29752_amd", "csrc")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 
-@pytest.fixture(scope="module")
-def asm(tmp_path_factory):
+def _device_asm(tmp_path_factory, src):
     if not os.path.exists(HIPCC) and shutil.which("hipcc") is None:
         pytest.skip("hipcc not available")
-    out = str(tmp_path_factory.mktemp("asm") / "gemm_tile.s")
+    out = str(tmp_path_factory.mktemp("asm") / (src + ".s"))
     cmd = [HIPCC, "--offload-arch=gfx950", "-O3", "-std=c++17", "-x", "hip",
            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-           "--cuda-device-only", "-S", os.path.join(CSRC, "gemm_tile.hip"), "-o", out]
+           "--cuda-device-only", "-S", os.path.join(CSRC, src), "-o", out]
     r = subprocess.run(cmd, capture_output=True, text=True)
     assert r.returncode == 0, r.stderr[-2000:]
     return open(out).read()
+
+
+@pytest.fixture(scope="module")
+def asm(tmp_path_factory):
+    return _device_asm(tmp_path_factory, "gemm_tile.hip")
+
+
+@pytest.fixture(scope="module")
+def grouped_asm(tmp_path_factory):
+    return _device_asm(tmp_path_factory, "grouped.hip")
 
 
 TILES = [(256, 256), (256, 128), (128, 256), (128, 128), (128, 64), (64, 128), (64, 64)]
@@ -127,3 +136,14 @@ def test_stream_k_kernel_codegen(asm, bm, bn):
     assert len(entry) == 1
     for key in (".vgpr_spill_count", ".sgpr_spill_count"):
         assert re.findall(re.escape(key) + r":\s+(\d+)", entry[0]) == ["0"], key
+
+
+def test_grouped_kernels_no_spills(grouped_asm):
+    """Every persistent grouped kernel (each tile shape, all-aligned and general bodies) keeps
+    its registers: no spills."""
+    meta = grouped_asm[grouped_asm.index("amdhsa.kernels:"):]
+    entries = [e for e in meta.split("\n  - ") if re.search(r"\.name:\s+_ZN2sg15sg_gemm_grouped", e)]
+    assert len(entries) == 2 * len(TILES)
+    for e in entries:
+        for key in (".vgpr_spill_count", ".sgpr_spill_count"):
+            assert re.findall(re.escape(key) + r":\s+(\d+)", e) == ["0"], (key, e[:200])
