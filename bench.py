@@ -919,8 +919,9 @@ def run_serve(args, sg, torch, ctx, table=None):
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2, help="timed passes over the sweep")
-    ap.add_argument("--warmup", type=int, default=1, help="untimed passes before timing")
+    ap.add_argument("--steps", type=int, default=10,
+                    help="timed steps: timed runs of every shape's plan, taken `reps` at a time")
+    ap.add_argument("--warmup", type=int, default=2, help="untimed passes before timing")
     ap.add_argument("--reps", type=int, default=5,
                     help="timed runs per shape in the table measurement (one more is discarded), and "
                          "the least number of timed runs per shape over all timed passes")
