@@ -844,6 +844,11 @@ def run_offgrid(args, sg, torch, ctx, stream):
     r = secs["naive_pad_to_tile"] / secs["dp_split_pad"]
     out["dp_vs_naive"] = {"mean_speedup": float(r.mean()), "median_speedup": float(np.median(r)),
                           "frac_faster": float(np.mean(r > 1.0)), "frac_faster_10pct": float(np.mean(r > 1.1))}
+    r = secs["best_of_n"] / secs["dp_split_pad"]
+    out["dp_vs_best_of_n"] = {"mean_speedup": float(r.mean()), "median_speedup": float(np.median(r)),
+                              "frac_faster": float(np.mean(r > 1.0)), "frac_faster_5pct": float(np.mean(r > 1.05)),
+                              "frac_slower_5pct": float(np.mean(r < 1 / 1.05))}
+    out["variants"] = [sg.variant_info(v).name for v in variants]
     ctx.set_table(None)
     return out
 
@@ -1313,6 +1318,8 @@ def main():
         "plain_variant": sg.variant_info(plain_variant).name,
         "gain_vs_plain": gain(ex, plain),
         "gain_vs_best_of_n": gain(ex, bestn),
+        "best_single_variant": sg.variant_info(best_single).name,
+        "gain_vs_best_single": gain(ex, stacks["best_single_%s" % sg.variant_info(best_single).name]),
         "noise_floor": noise,
         "stacks": stacks,
         "first_principles": first_principles(sg, stack_secs, sizes, args.step, n),
