@@ -849,6 +849,13 @@ def run_offgrid(args, sg, torch, ctx, stream):
                               "frac_faster": float(np.mean(r > 1.0)), "frac_faster_5pct": float(np.mean(r > 1.05)),
                               "frac_slower_5pct": float(np.mean(r < 1 / 1.05))}
     out["variants"] = [sg.variant_info(v).name for v in variants]
+    acts = np.array([table.lookup(m, nn, k)["action"] for m, nn, k in shapes])
+    out["dp_vs_best_of_n_by_action"] = {
+        name: {"shapes": int(np.sum(acts == a)), "mean_speedup": float(r[acts == a].mean())}
+        for a, name in ((sg.ACT_AS_IS, "as_is"), (sg.ACT_PAD, "pad"), (sg.ACT_SPLIT_M, "split_m"),
+                        (sg.ACT_SPLIT_N, "split_n"), (sg.ACT_SPLIT_K, "split_k")) if np.any(acts == a)}
+    if args.dump:
+        np.savez(args.dump, shapes=np.array(shapes), actions=acts, **{k: v for k, v in secs.items()})
     ctx.set_table(None)
     return out
 

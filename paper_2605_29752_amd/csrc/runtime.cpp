@@ -137,9 +137,13 @@ void expand_plan(const sg_table* t, int64_t m0, int64_t n0, int64_t k0, int64_t 
         int rm, rn, rk;
         t->cell_coords(run, &rm, &rn, &rk);
         if (act == SG_ACT_PAD) {
+            // the target's variant over the target's M and N extent (tiles wholly outside the
+            // data exit at once) and over the region's own depth: depth beyond K would only add
+            // products of zeros -- more MFMA work, the same tile grid and the same result
+            (void)rk;
             L.Ml = std::max<int64_t>(m, (int64_t)(rm + 1) * g);
             L.Nl = std::max<int64_t>(n, (int64_t)(rn + 1) * g);
-            L.Kl = std::max<int64_t>(k, (int64_t)(rk + 1) * g);
+            L.Kl = k;
         } else {
             L.Ml = m; L.Nl = n; L.Kl = k;
         }
