@@ -309,8 +309,21 @@ int sg_table_lookup(const sg_table* t, int64_t M, int64_t N, int64_t K, sg_plan_
 int sg_table_values(const sg_table* t, int which, double* out, int64_t n);
 /* Variant ids of the table's T0 rows: writes min(cap, nvar) ids, *nvar = the row count. */
 int sg_table_variants(const sg_table* t, int* ids, int cap, int* nvar);
-/* Number of leaves (kernel launches, split-K reductions not counted) the plan of (M,N,K) runs. */
+/* Number of leaves (kernel launches, split-K reductions not counted) of the table plan of the
+ * cell covering (M,N,K).  Off the grid the runtime may run the cell's best variant instead
+ * (sg_table_plan_choice). */
 int sg_table_plan_leaves(const sg_table* t, int64_t M, int64_t N, int64_t K, int* out_leaves);
+/* Which plan SG_MODE_DP runs for (M,N,K).  A shape on the grid (every dimension a multiple of
+ * the step) runs the table plan of its cell (Sec. 7.1's O(1) lookup).  Off the grid the cell's
+ * plan, made for the cell's own sizes, is applied to the shape (splits at the same points, a
+ * pad to the target's M and N extent), and it runs only if its leaves -- each costed by its
+ * variant's T0 interpolated trilinearly between the grid cells that bracket the leaf's launch
+ * extent, clamped at the grid's ends -- are estimated no slower than the cell's best variant
+ * on the whole shape; else that variant runs alone.  est_plan and est_best receive the two
+ * estimates (seconds), *use_plan 1 when the table plan runs.  Host only; errors: SG_EINVAL
+ * (NULL, non-positive dims), SG_ERANGE (beyond the grid). */
+int sg_table_plan_choice(const sg_table* t, int64_t M, int64_t N, int64_t K, double* est_plan,
+                         double* est_best, int* use_plan);
 /* Binary file with a fingerprint (GPU architecture, compute-unit count, HIP runtime version, grid,
  * variant set, output type); load refuses a mismatch with SG_EMISMATCH unless `force` != 0.
  * Loading requires the current HIP device only when force == 0. */

@@ -115,6 +115,8 @@ _SIGS = {
     "sg_table_values": (_i32, [_p, _i32, _p, _i64]),
     "sg_table_variants": (_i32, [_p, _p, _i32, ctypes.POINTER(_i32)]),
     "sg_table_plan_leaves": (_i32, [_p, _i64, _i64, _i64, ctypes.POINTER(_i32)]),
+    "sg_table_plan_choice": (_i32, [_p, _i64, _i64, _i64, ctypes.POINTER(_d), ctypes.POINTER(_d),
+                                    ctypes.POINTER(_i32)]),
     "sg_table_group_count": (_i32, [_p, ctypes.POINTER(_i64)]),
     "sg_table_save": (_i32, [_p, ctypes.c_char_p]),
     "sg_table_load": (_i32, [ctypes.c_char_p, _i32, ctypes.POINTER(_p)]),
@@ -414,6 +416,14 @@ class Table:
         n = ctypes.c_int64()
         check(lib().sg_table_group_count(self.handle, ctypes.byref(n)))
         return n.value
+
+    def plan_choice(self, M: int, N: int, K: int) -> dict:
+        """Which plan the DP mode runs for (M, N, K): the table plan (always on the grid) or, off
+        the grid, the cell's best variant when that is estimated faster."""
+        ep, eb, use = ctypes.c_double(), ctypes.c_double(), ctypes.c_int()
+        check(lib().sg_table_plan_choice(self.handle, M, N, K, ctypes.byref(ep), ctypes.byref(eb),
+                                         ctypes.byref(use)))
+        return {"est_plan": ep.value, "est_best": eb.value, "use_plan": bool(use.value)}
 
     def plan_leaves(self, M: int, N: int, K: int) -> int:
         n = ctypes.c_int()

@@ -169,6 +169,40 @@ void expand_plan(const sg_table* t, int64_t m0, int64_t n0, int64_t k0, int64_t 
     }
 }
 
+// Off-grid plan choice.  A cell's plan was made for the cell's own sizes.  On a shape inside
+// the cell but off the grid, a split's pieces lose the alignment the split was chosen for while
+// still paying their extra launches, and a pad target may fit the shape worse than the cell's
+// own best variant.  So off the grid the plan is kept only when its leaves, each costed by its
+// variant's T0 interpolated at the leaf's launch extent, are estimated no slower than the
+// cell's best-of-N variant on the whole shape; on the grid the table's plan always runs.
+void plan_estimates(const sg_table* t, const std::vector<Leaf>& leaves, int64_t M, int64_t N,
+                    int64_t K, int best_variant, double* est_plan, double* est_best) {
+    double e = 0.0;
+    for (const Leaf& L : leaves) {
+        const int r = variant_row(t, L.variant);
+        e += r >= 0 ? t0_interp(t, r, L.Ml, L.Nl, L.Kl) : HUGE_VAL;
+    }
+    *est_plan = e;
+    const int rb = variant_row(t, best_variant);
+    *est_best = rb >= 0 ? t0_interp(t, rb, M, N, K) : HUGE_VAL;
+}
+
+// The table's plan for (M, N, K), or off the grid the cell's best variant alone when that is
+// estimated faster (above).  *use_plan (optional) says which.
+void table_plan(const sg_table* t, int64_t M, int64_t N, int64_t K, int cm, int cn, int ck,
+                std::vector<Leaf>& leaves, double* est_plan, double* est_best, int* use_plan) {
+    leaves.clear();
+    expand_plan(t, 0, 0, 0, M, N, K, cm, cn, ck, true, true, leaves);
+    const int vb = t->best_var[t->cell_index(cm, cn, ck)];
+    double ep = 0.0, eb = 0.0;
+    plan_estimates(t, leaves, M, N, K, vb, &ep, &eb);
+    const bool keep = t->on_grid(M, N, K) || ep <= eb;
+    if (!keep) leaves.assign(1, Leaf{0, 0, 0, M, N, K, M, N, K, vb, true, true});
+    if (est_plan) *est_plan = ep;
+    if (est_best) *est_best = eb;
+    if (use_plan) *use_plan = keep ? 1 : 0;
+}
+
 struct Problem {
     int64_t M, N, K;
     const uint16_t* A; int64_t lda;
@@ -200,7 +234,7 @@ int make_plan(const sg_ctx* ctx, const Problem& pr, int mode, int variant, std::
         leaves.push_back(Leaf{0, 0, 0, pr.M, pr.N, pr.K, pr.M, pr.N, pr.K, v, true, true});
         return SG_OK;
     }
-    expand_plan(t, 0, 0, 0, pr.M, pr.N, pr.K, cm, cn, ck, true, true, leaves);
+    table_plan(t, pr.M, pr.N, pr.K, cm, cn, ck, leaves, nullptr, nullptr, nullptr);
     return SG_OK;
 }
 
@@ -896,6 +930,17 @@ int time_plan_concurrent(sg_ctx* ctx, const Problem& pr, const std::vector<Leaf>
 }
 
 }  // namespace sg
+
+extern "C" int sg_table_plan_choice(const sg_table* t, int64_t M, int64_t N, int64_t K,
+                                    double* est_plan, double* est_best, int* use_plan) {
+    if (!t || !est_plan || !est_best || !use_plan) return fail(SG_EINVAL, "NULL argument");
+    if (M <= 0 || N <= 0 || K <= 0) return fail(SG_EINVAL, "plan choice needs positive dims");
+    int cm, cn, ck;
+    if (!t->covering_cell(M, N, K, &cm, &cn, &ck)) return fail(SG_ERANGE, "shape outside the table grid");
+    std::vector<Leaf> leaves;
+    table_plan(t, M, N, K, cm, cn, ck, leaves, est_plan, est_best, use_plan);
+    return SG_OK;
+}
 
 extern "C" int sg_sweep(sg_ctx* ctx, const sg_shape* shapes, int64_t n, int mode, int variant,
                         int c_dtype, int warmup, int reps, const void* A_pool, const void* B_pool,

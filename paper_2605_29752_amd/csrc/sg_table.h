@@ -41,6 +41,11 @@ struct sg_table {
         *n = (int)((c / grid.n_k) % grid.n_n);
         *m = (int)(c / ((int64_t)grid.n_k * grid.n_n));
     }
+    // Whether (M, N, K) is a grid point: every dimension a multiple of the step.
+    bool on_grid(int64_t M, int64_t N, int64_t K) const {
+        const int64_t g = grid.step;
+        return M % g == 0 && N % g == 0 && K % g == 0;
+    }
     // Cell whose size covers (M, N, K): ceil(dim / step) - 1 per axis; false if beyond the grid.
     bool covering_cell(int64_t M, int64_t N, int64_t K, int* m, int* n, int* k) const {
         const int64_t g = grid.step;
@@ -57,6 +62,10 @@ struct sg_table {
 namespace sg {
 // Fill T0best/best_var/T1/T2/action/arg from T0.
 int build_dp(sg_table* t);
+// T0 of variant row `row` interpolated at (M, N, K) (trilinear between the bracketing cells,
+// clamped to the grid), and the T0 row of a variant id (-1 if the table has none).
+double t0_interp(const sg_table* t, int row, int64_t M, int64_t N, int64_t K);
+int variant_row(const sg_table* t, int variant);
 int measure_t0(struct ::sg_ctx* ctx, const std::vector<sg_shape>& order,
                const std::vector<int64_t>& cells, const int* variants, int nvar, int c_dtype,
                int warmup, int reps, const void* A_pool, const void* B_pool, void* C_pool,

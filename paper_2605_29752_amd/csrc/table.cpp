@@ -119,6 +119,43 @@ static std::string device_fingerprint(int* cus, int* rt) {
     return std::string(p.gcnArchName);   // the marketing name is not stable (profilers blank it)
 }
 
+// T0 of row `row` at extents (M, N, K): trilinear interpolation between the grid cells that
+// bracket each extent (cell c holds size (c + 1) g), clamped to the first and last cells.  At a
+// grid point it is the measured value itself.
+double t0_interp(const sg_table* t, int row, int64_t M, int64_t N, int64_t K) {
+    const double g = (double)t->grid.step;
+    auto axis = [g](int64_t d, int n, int* lo, int* hi, double* f) {
+        const double x = (double)d / g;             // cell lo holds (lo + 1) g
+        if (x <= 1.0) { *lo = *hi = 0; *f = 0.0; return; }
+        if (x >= (double)n) { *lo = *hi = n - 1; *f = 0.0; return; }
+        const int c = (int)std::floor(x) - 1;
+        *lo = c;
+        *hi = c + 1;
+        *f = x - (double)(c + 1);
+    };
+    int m0, m1, n0, n1, k0, k1;
+    double fm, fn, fk;
+    axis(M, t->grid.n_m, &m0, &m1, &fm);
+    axis(N, t->grid.n_n, &n0, &n1, &fn);
+    axis(K, t->grid.n_k, &k0, &k1, &fk);
+    const double* T = t->T0.data() + (size_t)row * (size_t)t->cells();
+    auto at = [&](int a, int b, int c) { return T[t->cell_index(a, b, c)]; };
+    double v = 0.0;
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b)
+            for (int c = 0; c < 2; ++c) {
+                const double w = (a ? fm : 1.0 - fm) * (b ? fn : 1.0 - fn) * (c ? fk : 1.0 - fk);
+                if (w != 0.0) v += w * at(a ? m1 : m0, b ? n1 : n0, c ? k1 : k0);
+            }
+    return v;
+}
+
+int variant_row(const sg_table* t, int variant) {
+    for (int r = 0; r < t->nvar; ++r)
+        if (t->variants[r] == variant) return r;
+    return -1;
+}
+
 }  // namespace sg
 
 using namespace sg;

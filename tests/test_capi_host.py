@@ -4,6 +4,8 @@ import ctypes
 import os
 import re
 
+import math
+
 import numpy as np
 import pytest
 
@@ -93,6 +95,52 @@ def test_table_lookup_off_grid_and_range():
     assert e.value.code == sg.SG_ERANGE
     with pytest.raises(sg.SGError):
         t.lookup(0, 5, 5)
+
+
+def test_plan_choice_interpolates_t0_between_cells():
+    # T0 multilinear in (M, N, K) is reproduced exactly by trilinear interpolation inside the
+    # grid, and clamped to the first / last cell outside it
+    g, n = 128, 4
+    sizes = (np.arange(n) + 1) * g
+    M3, N3, K3 = np.meshgrid(sizes, sizes, sizes, indexing="ij")
+    f = lambda m, nn, k: (1.0 + 0.001 * m) * (2.0 + 0.002 * nn) * (0.5 + 0.003 * k)
+    T0 = f(M3, N3, K3)[None].astype(np.float64)
+    t = sg.Table.from_t0(g, n, n, n, T0, [12])
+    for (M, N, K) in [(200, 300, 400), (129, 511, 256), (384, 130, 500), (257, 257, 257)]:
+        assert math.isclose(t.plan_choice(M, N, K)["est_best"], f(M, N, K), rel_tol=1e-12)
+    assert math.isclose(t.plan_choice(5, 300, 128)["est_best"], f(128, 300, 128), rel_tol=1e-12)
+
+
+def test_plan_choice_on_grid_always_runs_the_table_plan():
+    rng = np.random.default_rng(7)
+    T0 = rng.uniform(1.0, 10.0, size=(2, 4, 4, 4))
+    t = sg.Table.from_t0(128, 4, 4, 4, T0, [0, 12])
+    for cell in np.ndindex(4, 4, 4):
+        M, N, K = [(c + 1) * 128 for c in cell]
+        ch = t.plan_choice(M, N, K)
+        assert ch["use_plan"]
+        if t.lookup(M, N, K)["action"] == sg.ACT_AS_IS:
+            assert ch["est_plan"] == ch["est_best"] == T0.min(axis=0)[cell]
+
+
+def test_plan_choice_off_grid_drops_a_split_that_no_longer_pays():
+    # one variant along M only: 512 splits into 128 + 384 (2.5 + 3.2 < 7) on the grid
+    T0 = np.array([2.5, 3.0, 3.2, 7.0]).reshape(1, 4, 1, 1)
+    t = sg.Table.from_t0(128, 4, 1, 1, T0, [12])
+    r = t.lookup(512, 128, 128)
+    assert r["action"] == sg.ACT_SPLIT_M and r["arg"] == 1 and r["t2"] == 5.7
+    assert t.plan_choice(512, 128, 128)["use_plan"]
+    # M = 390 (cell 512): pieces 128 + 262 cost 2.5 + 3.009, the variant alone 3.378
+    ch = t.plan_choice(390, 128, 128)
+    assert math.isclose(ch["est_plan"], 2.5 + 3.0 + 6 / 128 * 0.2, rel_tol=1e-12)
+    assert math.isclose(ch["est_best"], 3.2 + 6 / 128 * 3.8, rel_tol=1e-12)
+    assert not ch["use_plan"]
+    # M = 500: pieces 128 + 372 cost 5.68, the variant alone 6.64: the split still pays
+    ch = t.plan_choice(500, 128, 128)
+    assert ch["use_plan"] and ch["est_plan"] < ch["est_best"]
+    with pytest.raises(sg.SGError) as e:
+        t.plan_choice(513, 1, 1)
+    assert e.value.code == sg.SG_ERANGE
 
 
 def test_table_rejects_bad_t0():
