@@ -854,8 +854,13 @@ def run_offgrid(args, sg, torch, ctx, stream):
         name: {"shapes": int(np.sum(acts == a)), "mean_speedup": float(r[acts == a].mean())}
         for a, name in ((sg.ACT_AS_IS, "as_is"), (sg.ACT_PAD, "pad"), (sg.ACT_SPLIT_M, "split_m"),
                         (sg.ACT_SPLIT_N, "split_n"), (sg.ACT_SPLIT_K, "split_k")) if np.any(acts == a)}
+    choice = [table.plan_choice(m, nn, k) for m, nn, k in shapes]
+    use = np.array([c["use_plan"] for c in choice])
+    out["dp_runs_table_plan"] = float(use.mean())
     if args.dump:
-        np.savez(args.dump, shapes=np.array(shapes), actions=acts, **{k: v for k, v in secs.items()})
+        np.savez(args.dump, shapes=np.array(shapes), actions=acts, use_plan=use,
+                 est_plan=np.array([c["est_plan"] for c in choice]),
+                 est_best=np.array([c["est_best"] for c in choice]), **{k: v for k, v in secs.items()})
     ctx.set_table(None)
     return out
 
