@@ -318,8 +318,8 @@ int sg_table_plan_leaves(const sg_table* t, int64_t M, int64_t N, int64_t K, int
  * plan, made for the cell's own sizes, is applied to the shape (splits at the same points, a
  * pad to the target's M and N extent), and it runs only if its leaves -- each costed by its
  * variant's T0 interpolated trilinearly between the grid cells that bracket the leaf's launch
- * extent, clamped at the grid's ends -- are estimated no slower than the cell's best variant
- * on the whole shape; else that variant runs alone.  est_plan and est_best receive the two
+ * extent, clamped at the grid's ends -- are estimated at least 5 % faster than the cell's best
+ * variant on the whole shape; else that variant runs alone.  est_plan and est_best receive the two
  * estimates (seconds), *use_plan 1 when the table plan runs.  Host only; errors: SG_EINVAL
  * (NULL, non-positive dims), SG_ERANGE (beyond the grid). */
 int sg_table_plan_choice(const sg_table* t, int64_t M, int64_t N, int64_t K, double* est_plan,
