@@ -981,7 +981,7 @@ def main():
     ap.add_argument("--serve-tile", type=int, default=3)
     ap.add_argument("--serve-small-m", type=int, default=64)
     ap.add_argument("--serve-small-tile", type=int, default=6)
-    ap.add_argument("--serve-solo-m", type=int, default=1024,
+    ap.add_argument("--serve-solo-m", type=int, default=256,
                     help="grouped serving launches requests with M above this on their own (0: never)")
     ap.add_argument("--serve-saturate", type=float, default=8.0,
                     help="seconds of closed-loop saturation per serving mode (0: skip)")
