@@ -1243,6 +1243,14 @@ def main():
     best_single = variants[int(np.argmax(means))]
     stacks["best_single_%s" % sg.variant_info(best_single).name] = \
         stack_stats(sg, T0all[variants.index(best_single)], sizes)
+    # the DP on one fixed tile (Table 10's "DP pad / split+pad (fixed tile)" rows), as the tables
+    # predict them: the same recurrence over the single variant's own T0
+    for row in sorted({plain_row, variants.index(best_single)}):
+        ft = sg.Table.from_t0(step, n, n, n, T0all[row][None], [variants[row]])
+        vname = sg.variant_info(variants[row]).name
+        stacks["dp_pad_fixed_%s_table" % vname] = stack_stats(sg, ft.values(1), sizes)
+        stacks["dp_split_pad_fixed_%s_table" % vname] = stack_stats(sg, ft.values(2), sizes)
+        ft.close()
     # gap-included (marker-interval) executions of the DP and plain stacks
     stacks["dp_split_pad_executed_interval"] = stack_stats(sg, exec_iv, sizes)
     stacks[pname + "_executed_interval"] = stack_stats(sg, plain_exec_iv, sizes)
