@@ -268,9 +268,9 @@ __global__ __launch_bounds__(256) void sg_splitk_reduce4(const float* ws, int64_
 int lds_bytes_of_tile(int tile) {
     switch (tile) {
         case 0: return dma_smem_bytes<256, 256, false, call_waves<256, 256>()>();
-        case 1: return dma_smem_bytes<256, 128>();
-        case 2: return dma_smem_bytes<128, 256>();
-        case 3: return dma_smem_bytes<128, 128>();
+        case 1: return dma_smem_bytes<256, 128, false, call_waves<256, 128>()>();
+        case 2: return dma_smem_bytes<128, 256, false, call_waves<128, 256>()>();
+        case 3: return dma_smem_bytes<128, 128, false, call_waves<128, 128>()>();
         case 4: return dma_smem_bytes<128, 64>();
         case 5: return dma_smem_bytes<64, 128>();
         case 6: return dma_smem_bytes<64, 64>();

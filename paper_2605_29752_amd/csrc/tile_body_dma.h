@@ -73,17 +73,20 @@ struct DmaTile {
 };
 
 // Waves per work-group of the direct-to-LDS kernels that run one tile shape per launch: eight
-// (2 x 4) for the 256-wide tiles, four (2 x 2) for the rest.  One wave on a SIMD draws LDS
+// (2 x 4) for the 256-wide tiles and 128 x 128, four (2 x 2) for the 64-wide ones.  One wave on a SIMD draws LDS
 // fragment reads at about 32 bytes per clock (a probe of conflict-free ds_read_b128 with eight
 // reads in flight: 131 bytes per clock per CU with four waves, 262 with eight), so a wave that
 // both reads its fragments and issues its MFMAs stalls on the reads; with two waves per SIMD one
 // multiplies while the other reads.  Measured against four waves (TFLOP/s): 256 x 256 at 4096^3
 // 976 -> 1,063 and at 4096 x 4096 x 1024 680 -> 785; 128 x 256 1,148 -> 1,205 at 4096^3 and
 // +15-29 % on mid-size shapes (2048^3 307 -> 384); 256 x 128 1,102 -> 1,151.  The 128 x 128 tile
-// gains on mid-size shapes (1024^3 149 -> 179) but loses 4-10 % on the large ones, where the
-// landscape spends most of its time in it, and the 64-wide tiles lose: they stay at four.
+// lost 4-10 % on the large shapes with eight waves until its fragment reads were pipelined
+// under its MFMAs; since then eight waves gain on average (over a seeded sample of 1,024
+// landscape cells: no split 459.9 -> 468.8 TFLOP/s, two splits 372.6 -> 377.8; 4096^3 1,083 ->
+// 1,095, 1024^3 156 -> 176; 4096 x 4096 x 128 loses, 244 -> 220).  The 64-wide tiles lose with
+// eight: they stay at four.
 template <int BM, int BN>
-constexpr int call_waves() { return (BM * BN >= 128 * 256) ? 8 : 4; }
+constexpr int call_waves() { return (BM * BN >= 128 * 128) ? 8 : 4; }
 
 template <int BM, int BN, bool DEEP = false, int NW = 4>
 constexpr int dma_smem_bytes() {
