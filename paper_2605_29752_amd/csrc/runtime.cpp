@@ -199,10 +199,12 @@ void table_plan(const sg_table* t, int64_t M, int64_t N, int64_t K, int cm, int 
                 std::vector<Leaf>& leaves, double* est_plan, double* est_best, int* use_plan) {
     leaves.clear();
     expand_plan(t, 0, 0, 0, M, N, K, cm, cn, ck, true, true, leaves);
+    const bool on_grid = t->on_grid(M, N, K);
+    if (on_grid && !est_plan && !est_best && !use_plan) return;     // the lookup alone
     const int vb = t->best_var[t->cell_index(cm, cn, ck)];
     double ep = 0.0, eb = 0.0;
     plan_estimates(t, leaves, M, N, K, vb, &ep, &eb);
-    const bool keep = t->on_grid(M, N, K) || ep <= (1.0 - kOffGridMargin) * eb;
+    const bool keep = on_grid || ep <= (1.0 - kOffGridMargin) * eb;
     if (!keep) leaves.assign(1, Leaf{0, 0, 0, M, N, K, M, N, K, vb, true, true});
     if (est_plan) *est_plan = ep;
     if (est_best) *est_best = eb;
