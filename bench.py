@@ -883,14 +883,19 @@ def run_serve(args, sg, torch, ctx, table=None):
     out = {"rate_req_s": args.serve_rate, "duration_s": args.serve_seconds,
            "warmup_s": args.serve_warmup, "tile": sg.variant_info(4 * args.serve_tile).name[:-6],
            "small_m": args.serve_small_m, "small_tile": sg.variant_info(4 * args.serve_small_tile).name[:-6],
-           "solo_m": args.serve_solo_m}
+           "solo_m": args.serve_solo_m, "tiles_from_table": bool(args.serve_tiles_from_table)}
+    if args.serve_tiles_from_table:
+        if table is None:
+            raise SystemExit("--serve-tiles-from-table needs a dispatch table (--table, or the sweep's)")
+        ctx.set_table(table)       # read once, when each server is created
 
     def server(mode, slots):
         return sg.Server(ctx, [(K, N, t.data_ptr(), N) for (K, N), t in zip(shapes, ws)],
                          hbm_budget=args.serve_budget_gb << 30, max_inflight=slots, max_group=64,
                          mode=mode, tile=args.serve_tile, max_m=8192, seed=5,
                          small_m=args.serve_small_m, small_tile=args.serve_small_tile,
-                         solo_m=args.serve_solo_m if mode == sg.SERVE_GROUPED else 0)
+                         solo_m=args.serve_solo_m if mode == sg.SERVE_GROUPED else 0,
+                         tiles_from_table=args.serve_tiles_from_table)
 
     sat = args.serve_saturate
     for name, mode in (("grouped", sg.SERVE_GROUPED), ("per_request", sg.SERVE_PER_REQUEST)):
@@ -929,6 +934,8 @@ def run_serve(args, sg, torch, ctx, table=None):
                              "grouped_vs_per_call_one_stream": ratio(g, out["per_call_one_stream_saturated"]),
                              "skinny_grouped_vs_per_request_4_slots": ratio(out["grouped_saturated_skinny"],
                                                                             out["per_request_saturated_skinny"])}
+    if args.serve_tiles_from_table:
+        ctx.set_table(None)
     del ws
     return out
 
@@ -981,6 +988,8 @@ def main():
     ap.add_argument("--serve-tile", type=int, default=3)
     ap.add_argument("--serve-small-m", type=int, default=64)
     ap.add_argument("--serve-small-tile", type=int, default=6)
+    ap.add_argument("--serve-tiles-from-table", action="store_true",
+                    help="serving tile classes from the dispatch table's best variant per request shape")
     ap.add_argument("--serve-solo-m", type=int, default=256,
                     help="grouped serving launches requests with M above this on their own (0: never)")
     ap.add_argument("--serve-saturate", type=float, default=8.0,
@@ -1022,7 +1031,7 @@ def main():
               "vs_baseline": None, "dtype": "bf16", "data": "synthetic", "device": props.name}
 
     if args.workload == "serve":
-        res = run_serve(args, sg, torch, ctx)
+        res = run_serve(args, sg, torch, ctx, sg.Table.load(args.table) if args.table else None)
         g, p = res["grouped"], res["per_request"]
         print(json.dumps(dict(
             metric="served p99 latency, continuous batching (Poisson %.0f req/s)" % args.serve_rate,

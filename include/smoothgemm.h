@@ -403,7 +403,8 @@ int sg_graph_destroy(sg_graph* graph);
  * allocation; stages each admitted request's A (copied from a resident pool of N(0, a_scale)
  * activations at a per-request offset derived from (seed, id)); and launches admitted requests
  * as one grouped kernel on any free stream slot, so new work overlaps running work.  Every
- * request belongs to a tile class (small_tile for M <= small_m, else tile); a launch takes the
+ * request belongs to a tile class (small_tile for M <= small_m, else tile; or, with
+ * tiles_from_table, the tile of the dispatch table's best variant for its shape); a launch takes the
  * oldest admitted request and up to max_group - 1 admitted requests after it of its class.  A
  * request with M > solo_m (solo_m > 0) is launched on its own even in grouped mode: it fills the
  * device by itself, and in a group it would only wait for the group's other members.  A
@@ -431,6 +432,12 @@ typedef struct sg_server_cfg {
     int64_t small_m;            /* requests with M <= small_m run with small_tile (0: none)      */
     int small_tile;             /* tile shape index 0..6 for those skinny requests               */
     int64_t solo_m;             /* requests with M > solo_m launch alone (0: every request groups) */
+    int tiles_from_table;       /* 1: a request's tile class is the tile of the best variant of the
+                                   context's dispatch table (held at creation) for its (M, N, K),
+                                   each axis clamped to the grid; split-K and stream-K variants give
+                                   their tile, the deep-K 64 x 64 the 64 x 64 tile; small_m,
+                                   small_tile and tile are then unused.  SG_ENOTABLE without a
+                                   table.  0: the small_m rule                                      */
 } sg_server_cfg;
 typedef struct sg_request { uint64_t id; int64_t M; int weight; } sg_request;
 typedef struct sg_completion {

@@ -160,7 +160,7 @@ class sg_server_cfg(ctypes.Structure):
                 ("queue_cap", _i32), ("mode", _i32), ("tile", _i32), ("keep_results", _i32),
                 ("n_weights", _i32), ("weights", ctypes.POINTER(sg_weight)), ("max_m", _i64),
                 ("seed", ctypes.c_uint64), ("a_scale", _d), ("small_m", _i64), ("small_tile", _i32),
-                ("solo_m", _i64)]
+                ("solo_m", _i64), ("tiles_from_table", _i32)]
 
 
 class sg_request(ctypes.Structure):
@@ -631,14 +631,16 @@ class Server:
     def __init__(self, ctx: "Context", weights, *, hbm_budget: int, max_inflight: int = 4,
                  max_group: int = 64, queue_cap: int = 1 << 20, mode: int = SERVE_GROUPED,
                  tile: int = 3, keep_results: bool = False, max_m: int = 8192, seed: int = 5,
-                 a_scale: float = 0.02, small_m: int = 64, small_tile: int = 6, solo_m: int = 0):
+                 a_scale: float = 0.02, small_m: int = 64, small_tile: int = 6, solo_m: int = 0,
+                 tiles_from_table: bool = False):
         """weights: [(K, N, B_ptr, ldb), ...] device-resident BF16 matrices.  Requests with
-        M <= small_m run with tile shape small_tile, the others with `tile`; requests with
-        M > solo_m (solo_m > 0) are launched on their own, never in a group."""
+        M <= small_m run with tile shape small_tile, the others with `tile`, or with
+        tiles_from_table the tile of the context table's best variant for their shape; requests
+        with M > solo_m (solo_m > 0) are launched on their own, never in a group."""
         self._w = (sg_weight * len(weights))(*[sg_weight(*[int(x) for x in w]) for w in weights])
         cfg = sg_server_cfg(hbm_budget, max_inflight, max_group, queue_cap, mode, tile,
                             1 if keep_results else 0, len(weights), self._w, max_m, seed, a_scale,
-                            small_m, small_tile, solo_m)
+                            small_m, small_tile, solo_m, 1 if tiles_from_table else 0)
         h = ctypes.c_void_p()
         check(lib().sg_server_create(ctx.handle, ctypes.byref(cfg), ctypes.byref(h)))
         self.handle = h

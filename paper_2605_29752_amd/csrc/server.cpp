@@ -25,6 +25,7 @@
 #include <vector>
 
 #include "sg_internal.h"
+#include "sg_table.h"
 
 using namespace sg;
 
@@ -121,6 +122,9 @@ struct sg_server {
     Pool* pool = nullptr;
     std::vector<Slot> slots;
     std::chrono::steady_clock::time_point t0;
+    // tiles_from_table: tile class of a request of weight w whose M falls in table row-cell c
+    int table_step = 0;
+    std::vector<std::vector<int>> table_tile;   // [weight][M cell]
 
     std::mutex mu;                    // guards everything below
     std::deque<uint64_t> pending;     // submitted, not admitted
@@ -331,7 +335,6 @@ void worker_main(sg_server* sv) {
 extern "C" {
 
 int sg_server_create(sg_ctx* ctx, const sg_server_cfg* cfg, sg_server** out) {
-    (void)ctx;
     if (!cfg || !out) return fail(SG_EINVAL, "NULL argument");
     *out = nullptr;
     if (cfg->hbm_budget < (1u << 20) || cfg->max_inflight < 1 || cfg->max_inflight > 16 ||
@@ -346,8 +349,29 @@ int sg_server_create(sg_ctx* ctx, const sg_server_cfg* cfg, sg_server** out) {
         if (w.K <= 0 || w.N <= 0 || !w.B || w.ldb < w.N) return fail(SG_EINVAL, "bad weight");
         maxK = std::max(maxK, w.K);
     }
+    if (cfg->tiles_from_table != 0 && cfg->tiles_from_table != 1) return fail(SG_EINVAL, "bad server configuration");
+    const sg_table* tab = cfg->tiles_from_table ? (ctx ? ctx_table(ctx) : nullptr) : nullptr;
+    if (cfg->tiles_from_table && !tab)
+        return fail(SG_ENOTABLE, "tiles_from_table needs a dispatch table on the context");
     sg_server* sv = new (std::nothrow) sg_server();
     if (!sv) return fail(SG_ENOMEM, "server allocation failed");
+    if (tab) {
+        // per weight and M cell, the tile of the table's best variant at (M cell, N, K), each
+        // axis clamped to the grid (a shape beyond it takes the largest cell's choice); a
+        // split-K or stream-K variant gives its tile, the deep-K 64 x 64 the 64 x 64 tile
+        const sg_grid& g = tab->grid;
+        auto cell_of = [&](int64_t d, int n) { return (int)std::min<int64_t>(n - 1, std::max<int64_t>(0, (d + g.step - 1) / g.step - 1)); };
+        sv->table_step = g.step;
+        sv->table_tile.resize(cfg->n_weights);
+        for (int i = 0; i < cfg->n_weights; ++i) {
+            const int cn = cell_of(cfg->weights[i].N, g.n_n), ck = cell_of(cfg->weights[i].K, g.n_k);
+            for (int cm = 0; cm < g.n_m; ++cm) {
+                int t = variant_tile(tab->best_var[tab->cell_index(cm, cn, ck)]);
+                if (t >= kNumGroupTiles) t = kNumGroupTiles - 1;
+                sv->table_tile[i].push_back(t);
+            }
+        }
+    }
     sv->cfg = *cfg;
     sv->weights.assign(cfg->weights, cfg->weights + cfg->n_weights);
     sv->cfg.weights = sv->weights.data();
@@ -402,7 +426,13 @@ int sg_server_submit(sg_server* sv, const sg_request* req, double arrival_s, uin
     r.id = req->id;
     r.M = req->M;
     r.w = req->weight;
-    r.tile = req->M <= sv->cfg.small_m ? sv->cfg.small_tile : sv->cfg.tile;
+    if (!sv->table_tile.empty()) {
+        const std::vector<int>& tt = sv->table_tile[req->weight];
+        const int64_t cm = std::min<int64_t>((int64_t)tt.size() - 1, (req->M + sv->table_step - 1) / sv->table_step - 1);
+        r.tile = tt[(size_t)std::max<int64_t>(0, cm)];
+    } else {
+        r.tile = req->M <= sv->cfg.small_m ? sv->cfg.small_tile : sv->cfg.tile;
+    }
     r.solo = sv->cfg.solo_m > 0 && req->M > sv->cfg.solo_m;
     const int64_t span = sv->act_elems - req->M * w.K;
     r.a_offset = (int64_t)(mix64(sv->cfg.seed ^ mix64(req->id + 1)) % (uint64_t)(span / 8 + 1)) * 8;

@@ -31,12 +31,14 @@ def weights():
     return shapes, ws, host
 
 
-def _serve_and_check(ctx, weights, mode, budget, n_req=60, max_group=8, solo_m=0):
+def _serve_and_check(ctx, weights, mode, budget, n_req=60, max_group=8, solo_m=0,
+                     tiles_from_table=False, expect_tile=lambda M: 6 if M <= 64 else 3):
     import torch
     shapes, ws, host = weights
     srv = sg.Server(ctx, [(K, N, t.data_ptr(), N) for (K, N), t in zip(shapes, ws)],
                     hbm_budget=budget, max_inflight=2, max_group=max_group, mode=mode, tile=3,
-                    keep_results=True, max_m=600, seed=ASEED, solo_m=solo_m)
+                    keep_results=True, max_m=600, seed=ASEED, solo_m=solo_m,
+                    tiles_from_table=tiles_from_table)
     rng = np.random.default_rng(1)
     for i in range(n_req):
         srv.submit(i, int(rng.integers(1, 601)), int(rng.integers(0, len(shapes))))
@@ -54,7 +56,7 @@ def _serve_and_check(ctx, weights, mode, budget, n_req=60, max_group=8, solo_m=0
     assert st["peak_bytes"] <= budget and st["completed"] == n_req
     say("mode", mode, "launches", st["launches"], "peak bytes", st["peak_bytes"])
     for (M, N, K, w, status, a_offset, A, Cb, tile, gsize) in comps:
-        assert tile == (6 if M <= 64 else 3)
+        assert tile == expect_tile(M)
         assert 1 <= gsize <= (max_group if mode == sg.SERVE_GROUPED else 1)
         if solo_m and M > solo_m:
             assert gsize == 1, 'a solo request was grouped'
@@ -83,6 +85,33 @@ def test_served_equals_alone_grouped_solo(ctx, weights):
     st = _serve_and_check(ctx, weights, sg.SERVE_GROUPED, 64 << 20, solo_m=300)
     n_solo = sum(1 for m in st["Ms"] if m > 300)
     assert 0 < n_solo < 60 and n_solo < st["launches"] <= 60
+
+
+def test_served_equals_alone_tiles_from_table(ctx, weights):
+    # a host-built dispatch table whose best variant changes with M (64x64 for M <= 128,
+    # 128x128 up to 384, 256x128 above): requests take those tile classes, and a served
+    # result still equals the same tile alone
+    n_m, n_n, n_k = 5, 8, 8
+    T0 = np.ones((3, n_m, n_n, n_k))
+    best = [0, 1, 1, 2, 2]
+    for cm in range(n_m):
+        T0[best[cm], cm] = 0.5
+    t = sg.Table.from_t0(128, n_m, n_n, n_k, T0, [24, 12, 4])
+    tile_of = {0: 6, 1: 3, 2: 1}
+    ctx.set_table(t)
+    try:
+        st = _serve_and_check(ctx, weights, sg.SERVE_GROUPED, 64 << 20, tiles_from_table=True,
+                              expect_tile=lambda M: tile_of[best[min(n_m - 1, (M + 127) // 128 - 1)]])
+    finally:
+        ctx.set_table(None)
+        t.close()
+    assert st["completed"] == 60
+    # without a table on the context the option is refused
+    shapes, ws, host = weights
+    with pytest.raises(sg.SGError) as e:
+        sg.Server(ctx, [(K, N, w.data_ptr(), N) for (K, N), w in zip(shapes, ws)], hbm_budget=8 << 20,
+                  max_m=600, seed=ASEED, tiles_from_table=True)
+    assert e.value.code == sg.SG_ENOTABLE
 
 
 def test_served_equals_alone_per_request(ctx, weights):
