@@ -868,7 +868,8 @@ def run_offgrid(args, sg, torch, ctx, stream):
 def run_serve(args, sg, torch, ctx, table=None):
     """Config 5: Poisson requests over four transformer-layer weights (the full duration), grouped
     continuous batching versus per-request dispatch on the same four stream slots, same arrivals
-    and tile classes (M <= 64 on the small tile, the rest on the main tile).  Then saturation,
+    and tile classes (the dispatch table's best variant per request shape when a table is at
+    hand, else M <= 64 on the small tile and the rest on the main tile).  Then saturation,
     closed loop with a fixed number of requests outstanding: grouped, per-request on four slots,
     per-call dispatch on one stream (each request launched alone, in order, as a caller looping
     over gemm calls would), and the same grouped / per-request pair on a skinny mix (M <= 64,
@@ -883,10 +884,12 @@ def run_serve(args, sg, torch, ctx, table=None):
     out = {"rate_req_s": args.serve_rate, "duration_s": args.serve_seconds,
            "warmup_s": args.serve_warmup, "tile": sg.variant_info(4 * args.serve_tile).name[:-6],
            "small_m": args.serve_small_m, "small_tile": sg.variant_info(4 * args.serve_small_tile).name[:-6],
-           "solo_m": args.serve_solo_m, "tiles_from_table": bool(args.serve_tiles_from_table)}
-    if args.serve_tiles_from_table:
-        if table is None:
-            raise SystemExit("--serve-tiles-from-table needs a dispatch table (--table, or the sweep's)")
+           "solo_m": args.serve_solo_m}
+    # tile classes from the dispatch table's best variant per request shape when a table is at
+    # hand (the sweep's, or --table), else the fixed classes (M <= small_m on the small tile)
+    use_table = table is not None and not args.serve_fixed_tiles
+    out["tiles_from_table"] = use_table
+    if use_table:
         ctx.set_table(table)       # read once, when each server is created
 
     def server(mode, slots):
@@ -895,7 +898,7 @@ def run_serve(args, sg, torch, ctx, table=None):
                          mode=mode, tile=args.serve_tile, max_m=8192, seed=5,
                          small_m=args.serve_small_m, small_tile=args.serve_small_tile,
                          solo_m=args.serve_solo_m if mode == sg.SERVE_GROUPED else 0,
-                         tiles_from_table=args.serve_tiles_from_table)
+                         tiles_from_table=use_table)
 
     sat = args.serve_saturate
     for name, mode in (("grouped", sg.SERVE_GROUPED), ("per_request", sg.SERVE_PER_REQUEST)):
@@ -934,7 +937,7 @@ def run_serve(args, sg, torch, ctx, table=None):
                              "grouped_vs_per_call_one_stream": ratio(g, out["per_call_one_stream_saturated"]),
                              "skinny_grouped_vs_per_request_4_slots": ratio(out["grouped_saturated_skinny"],
                                                                             out["per_request_saturated_skinny"])}
-    if args.serve_tiles_from_table:
+    if use_table:
         ctx.set_table(None)
     del ws
     return out
@@ -988,8 +991,8 @@ def main():
     ap.add_argument("--serve-tile", type=int, default=3)
     ap.add_argument("--serve-small-m", type=int, default=64)
     ap.add_argument("--serve-small-tile", type=int, default=6)
-    ap.add_argument("--serve-tiles-from-table", action="store_true",
-                    help="serving tile classes from the dispatch table's best variant per request shape")
+    ap.add_argument("--serve-fixed-tiles", action="store_true",
+                    help="serve with the fixed tile classes even when a dispatch table is at hand")
     ap.add_argument("--serve-solo-m", type=int, default=256,
                     help="grouped serving launches requests with M above this on their own (0: never)")
     ap.add_argument("--serve-saturate", type=float, default=8.0,
