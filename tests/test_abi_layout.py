@@ -1,5 +1,6 @@
-"""The binding's ctypes structures match the C header field by field (offset and size), and
-every structure the header declares with a binding counterpart has one.  A C program built
+"""The binding's ctypes structures match the C header field by field (offset and size), every
+structure the header declares has a binding counterpart, and every declared function is bound
+with the header's number of parameters.  A C program built
 from the header with the host compiler prints the layout; no GPU is involved."""
 import ctypes
 import os
@@ -72,3 +73,28 @@ def test_every_header_struct_is_bound_field_for_field():
     assert set(declared) <= set(bound), "structures without a binding: %s" % sorted(set(declared) - set(bound))
     for name, fields in declared.items():
         assert [f[0] for f in bound[name]._fields_] == fields, "%s: fields differ from the header" % name
+
+
+def _header_prototypes():
+    """{function name: parameter count} of every prototype in the header."""
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    text = re.sub(r"#[^\n]*", "", text)
+    out = {}
+    for m in re.finditer(r"\b(\w+)\s*\(([^;{}()]*)\)\s*;", text):
+        name, params = m.group(1), m.group(2).strip()
+        if name.startswith(("sg_", "gemm_")) and not name.endswith("_t"):
+            out[name] = 0 if params in ("", "void") else params.count(",") + 1
+    return out
+
+
+def test_binding_signatures_match_header_arity():
+    import paper_2605_29752_amd as sg
+    protos = _header_prototypes()
+    sigs = sg._SIGS
+    assert len(protos) > 40
+    missing = sorted(set(sigs) - set(protos))
+    assert not missing, "bound but not declared: %s" % missing
+    unbound = sorted(set(protos) - set(sigs))
+    assert not unbound, "declared but not bound: %s" % unbound
+    for name, (_, args) in sigs.items():
+        assert len(args) == protos[name], "%s: header has %d parameters, binding %d" % (name, protos[name], len(args))
