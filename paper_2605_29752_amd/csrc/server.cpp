@@ -10,8 +10,10 @@
 //      staged (A copied in from the resident activation pool) and launched as ONE persistent
 //      grouped kernel on that slot's stream, so work admitted while earlier groups run overlaps
 //      them on the device.  Per-request mode launches each request on its own instead.
-// Every request's output is computed by the same tile body whatever group it lands in, so a
-// result is bit-identical alone and in the mix (for the same tile shape).
+// A request's tile shape (its class) comes from M (a small tile for skinny requests) or, given a
+// dispatch table at creation, from the table's best variant for the request's shape; a launch
+// runs one class.  Every request's output is computed by the same tile body whatever group it
+// lands in, so a result is bit-identical alone and in the mix (for the same tile shape).
 #include <algorithm>
 #include <atomic>
 #include <chrono>
